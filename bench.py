@@ -1,0 +1,265 @@
+"""Benchmark of the batched negacyclic NTT path on one MI355X.
+
+Default workload (CKKS-level batch): N = 2^15, 16 RNS primes of 50-60 bits,
+64 ciphertexts x 2 polynomials = 128 polynomials per operand; one step is the
+whole path -- forward NTT of A and B, dyadic product, inverse NTT -- run as
+the library's fused polymul.  Inputs are resident in HBM before timing.
+
+Prints ONE JSON line: Gcoeff/s (B*L*N coefficients per transform, three
+transforms per step), the roofline of the dominant kernel (HIP-event timed on
+the launching stream), the per-polynomial-launch comparator, and the CPU
+oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "NTT Gcoeff/s & % HBM/int-mul roofline, batched vs per-poly; p50/p99 ct-mul"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="ckks_level", choices=["ckks_level", "ct_tensor", "plain4096"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-per-poly", action="store_true", help="skip the per-polynomial comparator")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU work for the oracle sample")
+    return ap.parse_args()
+
+
+def to_dev(a, torch):
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).to("cuda:0")
+
+
+def setup(name, torch, H):
+    """Device-resident operands and the step function for a workload."""
+    import workloads
+    if name == "ckks_level":
+        w = workloads.ckks_level()
+        t = H.Tables(w["log_n"], w["moduli"])
+        A, B = to_dev(w["a"], torch), to_dev(w["b"], torch)
+        out = torch.empty_like(A)
+        polys, L, n = A.shape[0], A.shape[1], A.shape[2]
+
+        def step():
+            H.polymul(t, A, B, out=out)
+
+        def per_poly_step():
+            for i in range(polys):
+                H.polymul(t, A[i:i + 1], B[i:i + 1], out=out[i:i + 1])
+
+        info = {"workload": "ckks_level", "N": n, "limbs": L, "polys_per_operand": polys,
+                "ops": "fwd(A), fwd(B), dyadic, inv (fused polymul)"}
+        return dict(step=step, per_poly=per_poly_step, coeffs=3 * polys * L * n, t=t, info=info, w=w,
+                    cpu=lambda k: cpu_ckks(w, k))
+    if name == "ct_tensor":
+        w = workloads.ct_tensor()
+        t = H.Tables(w["log_n"], w["moduli"])
+        C, D = to_dev(w["c"], torch), to_dev(w["d"], torch)
+        pairs, L, n = C.shape[0], C.shape[2], C.shape[3]
+        out = torch.empty((pairs, 3, L, n), dtype=torch.int64, device="cuda:0")
+
+        def step():
+            H.ct_tensor(t, C, D, out=out)
+
+        def per_poly_step():
+            for i in range(pairs):
+                H.ct_tensor(t, C[i:i + 1], D[i:i + 1], out=out[i:i + 1])
+
+        info = {"workload": "ct_tensor", "N": n, "limbs": L, "ct_pairs": pairs,
+                "ops": "fwd of c0,c1,d0,d1; tensor (c0d0, c0d1+c1d0, c1d1); inv of 3 outputs"}
+        return dict(step=step, per_poly=per_poly_step, coeffs=7 * pairs * L * n, t=t, info=info, w=w,
+                    cpu=lambda k: cpu_tensor(w, k), ctmul=pairs)
+    w = workloads.plain4096()
+    t = H.Tables(12, w["moduli"])
+    X = to_dev(w["x"], torch)
+
+    def step():
+        H.ntt_fwd(t, X)
+        H.ntt_inv(t, X)
+
+    def per_poly_step():
+        for i in range(X.shape[0]):
+            H.ntt_fwd(t, X[i:i + 1])
+            H.ntt_inv(t, X[i:i + 1])
+
+    info = {"workload": "plain4096", "N": 4096, "limbs": 1, "polys": 8, "ops": "fwd, inv"}
+    return dict(step=step, per_poly=per_poly_step, coeffs=2 * 8 * 4096, t=t, info=info, w=w,
+                cpu=lambda k: cpu_plain(w, k))
+
+
+# ---------------------------------------------------------------- CPU oracle
+def cpu_ckks(w, k):
+    import oracle
+    a, b = w["a"][:k], w["b"][:k]
+    t0 = time.perf_counter()
+    oracle.batch_polymul(a, b, w["moduli"])
+    dt = time.perf_counter() - t0
+    return dt, 3 * a.size
+
+
+def cpu_tensor(w, k):
+    import oracle
+    c, d = w["c"][:k], w["d"][:k]
+    t0 = time.perf_counter()
+    oracle.batch_ct_tensor_coeff(c, d, w["moduli"])
+    dt = time.perf_counter() - t0
+    return dt, 7 * c[:, 0].size
+
+
+def cpu_plain(w, k):
+    import oracle
+    x = w["x"]
+    t0 = time.perf_counter()
+    for _ in range(k):
+        X = oracle.batch_ntt(x, w["moduli"], +1)
+        oracle.batch_ntt(X, w["moduli"], -1)
+    dt = time.perf_counter() - t0
+    return dt, 2 * x.size * k
+
+
+def cpu_baseline(s, target_s):
+    import oracle
+    dt1, c1 = s["cpu"](1)                       # calibration: one batch entry
+    k = max(1, min(int(target_s / max(dt1, 1e-3)), 64))
+    dt, coeffs = s["cpu"](k) if k > 1 else (dt1, c1)
+    return {"value": coeffs / dt / 1e9, "unit": "Gcoeff/s", "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": "%d batch entr%s of the same workload (radix-2 oracle, OpenMP over (batch, limb)), %.1f s"
+                      % (k, "y" if k == 1 else "ies", dt)}
+
+
+# ---------------------------------------------------------------- roofline
+# 32-bit multiplies per unit of work (the algorithmic ALU count):
+MUL_BFLY = 10    # Shoup butterfly: hi64(W'Y) 4, lo64(WY) 3, lo64(Qq) 3
+MUL_PROD = 11    # Barrett product: 128-bit product 4, hi(z1 mu) 4, lo(q3 q) 3
+MUL_TENSOR = 37  # c0d0, c0d1 + c1d0, c1d1: four 128-bit products (16) + three reductions (21)
+
+
+def kernel_work(name, info):
+    """Algorithmic HBM bytes and 32-bit multiplies of ONE launch of `name` in
+    the benchmarked step: per-unit figures times the units one launch handles.
+    Bytes: every coefficient word a launch must read once and write once
+    (8 B each).  Multiplies: MUL_BFLY per butterfly, N/2 butterflies per
+    stage per polynomial limb, plus the products."""
+    n, L = info["N"], info["limbs"]
+    logn = n.bit_length() - 1
+    ec = {13: 1, 14: 2, 15: 3, 16: 4, 17: 4}.get(logn, 0)    # stages in the column pass
+    if info["workload"] == "ckks_level":
+        p = info["polys_per_operand"]
+        n_in, n_out, prod_mul = 2 * p, p, MUL_PROD * p * L * n
+    elif info["workload"] == "ct_tensor":
+        c = info["ct_pairs"]
+        n_in, n_out, prod_mul = 4 * c, 3 * c, MUL_TENSOR * c * L * n
+    else:
+        n_in = n_out = info["polys"]
+        prod_mul = 0
+    bfly = lambda polys, stages: MUL_BFLY * polys * L * (n // 2) * stages
+    base = name.split("<")[0]
+    if base == "k_cols_fwd":
+        return 16.0 * n_in * L * n, bfly(n_in, ec)
+    if base == "k_cols_inv":
+        return 16.0 * n_out * L * n, bfly(n_out, ec)
+    if base.startswith("k_prod"):
+        stages = logn - ec
+        return 8.0 * (n_in + n_out) * L * n, bfly(n_in + n_out, stages) + prod_mul
+    if base in ("k_fwd_whole", "k_inv_whole"):
+        return 16.0 * n_in * L * n, bfly(n_in, logn)
+    return None, None
+
+
+def roofline(prof, info, steps):
+    from paper_2109_14704_amd import roofline as R
+    # dominant kernel by total time
+    name, (ms, cnt) = max(prof.items(), key=lambda kv: kv[1][0])
+    per_launch_s = ms / 1e3 / cnt
+    nbytes, muls = kernel_work(name, info)
+    if nbytes is None:
+        return None, name, per_launch_s
+    t_hbm = nbytes / (R.HBM_PEAK_GBS * 1e9)
+    t_alu = muls / (R.VALU_PEAK_TOPS * 1e12)
+    if t_hbm >= t_alu:
+        ach = nbytes / per_launch_s / 1e9
+        rl = {"bound": "hbm", "achieved": round(ach, 1), "peak": R.HBM_PEAK_GBS, "unit": "GB/s",
+              "frac": round(ach / R.HBM_PEAK_GBS, 4)}
+    else:
+        ach = muls / per_launch_s / 1e12
+        rl = {"bound": "alu", "achieved": round(ach, 3), "peak": round(R.VALU_PEAK_TOPS, 2),
+              "unit": "T int32-mul/s", "frac": round(ach / R.VALU_PEAK_TOPS, 4)}
+    rl.update({"kernel": name, "launch_ms": round(per_launch_s * 1e3, 4), "traffic": R.stored_traffic(name)})
+    return rl, name, per_launch_s
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU; --gpus %d is not supported (the path shards by batch "
+              "with no exchange, see the design notes)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2109_14704_amd as H
+    H.lib()
+    print("bench: setting up workload %s" % args.workload, file=sys.stderr, flush=True)
+    s = setup(args.workload, torch, H)
+    step = s["step"]
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall
+    ms = e0.elapsed_time(e1) / args.steps
+    value = s["coeffs"] / (ms / 1e3) / 1e9
+    print("bench: %.3f ms/step (%.1f Gcoeff/s), wall %.3f s" % (ms, value, wall), file=sys.stderr, flush=True)
+
+    # per-kernel durations (HIP events on the launching stream), separate pass
+    H.prof_enable(True)
+    prof_steps = max(3, min(args.steps, 10))
+    for _ in range(prof_steps):
+        step()
+    torch.cuda.synchronize()
+    prof = H.prof_read()
+    H.prof_enable(False)
+    rl, kname, kdur = roofline(prof, s["info"], prof_steps)
+
+    result = {"metric": METRIC, "value": round(value, 3), "unit": "Gcoeff/s", "n_gpus": 1, "steps": args.steps,
+              "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+              "vs_baseline": None, "dtype": "u64", "data": "synthetic", "config": s["info"], "roofline": rl,
+              "kernels_ms": {k: round(v[0] / v[1], 4) for k, v in sorted(prof.items())}}
+    if "ctmul" in s:
+        result["ct_mul_per_s"] = round(s["ctmul"] / (ms / 1e3), 1)
+    if not args.no_per_poly:
+        s["per_poly"]()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 3
+        a.record()
+        for _ in range(reps):
+            s["per_poly"]()
+        b.record()
+        torch.cuda.synchronize()
+        pms = a.elapsed_time(b) / reps
+        result["per_poly"] = {"ms_per_step": round(pms, 4), "value": round(s["coeffs"] / (pms / 1e3) / 1e9, 3),
+                              "unit": "Gcoeff/s", "batched_speedup": round(pms / ms, 3)}
+    if not args.no_cpu:
+        print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
+        result["cpu_baseline"] = cpu_baseline(s, args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

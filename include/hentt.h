@@ -1,0 +1,152 @@
+/*
+ * hentt -- batched negacyclic NTT over RNS limbs for AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libhentt.so.  The operations follow arXiv 2109.14704:
+ *   - ring R_q = Z_q[x]/(x^N + 1), N = 2^log_n               (section II-A)
+ *   - polynomial product through the psi-twisted NTT:
+ *       a * b = INTT(NTT(a) (.) NTT(b))                       (section II-B)
+ *   - RNS: each limb (modulus q_l) is an independent sub-task (section II-B)
+ *   - ciphertext Mul tensor: (c0 d0, c0 d1 + c1 d0, c1 d1)    (section II-A, Mul)
+ *   - lazy Harvey butterflies, Algorithm 1                     (section III-B)
+ *   - fused multiply-add with one reduction (mad_mod)          (section III-A-1)
+ *
+ * Conventions.
+ *   - Data are uint64 words, layout [batch][limbs][N] (coefficient fastest);
+ *     ciphertexts are [batch][2][limbs][N], tensor outputs [batch][3][limbs][N].
+ *   - psi is the smallest primitive 2N-th root of unity mod q_l.
+ *   - NTT domain = bit-reversed order: NTT(a)[k] = sum_i a_i psi^(i (2 brv(k) + 1)).
+ *   - INTT includes N^-1 and the psi^-i untwist, so INTT(NTT(a)) == a exactly.
+ *   - Inputs must be canonical residues in [0, q_l); every output is canonical.
+ *   - Moduli: prime, q = 1 (mod 2N), 2^7 < q < 2^60 (16 q < 2^64 is what the
+ *     lazy butterflies need).
+ *
+ * Memory and streams.  Every data pointer is a DEVICE pointer owned by the
+ * caller, who keeps it alive until the work queued on `stream` completes.
+ * `stream` is a hipStream_t passed as void* (NULL = default stream).  Compute
+ * calls only enqueue work: they never synchronise the host.  Tables are
+ * owned by the library, immutable after creation, and may be shared across
+ * streams and threads.
+ *
+ * Errors.  Every call returns HENTT_OK (0) or a negative status; nothing is
+ * thrown across the ABI.  On HENTT_EHIP the HIP error code is available from
+ * hentt_last_hip_error() (thread-local).
+ */
+#ifndef HENTT_H
+#define HENTT_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HENTT_OK 0
+#define HENTT_EINVAL (-1)    /* null pointer, zero batch/limbs, log_n out of range, bad flags */
+#define HENTT_EMODULUS (-2)  /* modulus not prime, not 1 mod 2N, or out of (2^7, 2^60) */
+#define HENTT_ENOMEM (-3)    /* host or device allocation failed */
+#define HENTT_EHIP (-4)      /* a HIP runtime call failed; see hentt_last_hip_error() */
+
+#define HENTT_LOG_N_MIN 6
+#define HENTT_LOG_N_MAX 17
+#define HENTT_LIMBS_MAX 64
+
+/* ct_tensor flags: domain of the inputs and of the output. */
+#define HENTT_IN_COEFF 0u   /* c, d in the coefficient domain (forward transforms applied) */
+#define HENTT_IN_NTT 1u     /* c, d already in the NTT domain */
+#define HENTT_OUT_COEFF 0u  /* out in the coefficient domain (inverse transforms applied) */
+#define HENTT_OUT_NTT 2u    /* out left in the NTT domain */
+
+typedef struct hentt_tables hentt_tables;
+
+/* Twiddle tables for one modulus chain at one N (section II-B; Algorithm 1's
+ * root powers W and root power quotients W' = floor(W 2^64 / q)).
+ * log_n in [HENTT_LOG_N_MIN, HENTT_LOG_N_MAX]; moduli_host: `limbs` host
+ * words.  Builds on the host, uploads on `stream`, and waits for the upload.
+ * Device footprint: 32 N bytes per limb plus 64 bytes per limb.
+ * *out receives a handle the caller releases with hentt_tables_destroy. */
+int hentt_tables_create(uint32_t log_n, uint32_t limbs, const uint64_t *moduli_host, void *stream,
+                        hentt_tables **out);
+
+/* Releases a handle (a table or a view).  Device memory is freed when the last
+ * handle sharing it is released.  The caller makes sure no queued work still
+ * reads the tables (e.g. synchronises the stream first). */
+int hentt_tables_destroy(hentt_tables *t);
+
+/* A handle on the first `limbs` moduli of `t` (a lower level of the chain),
+ * sharing t's device memory.  Released with hentt_tables_destroy. */
+int hentt_tables_view(const hentt_tables *t, uint32_t limbs, hentt_tables **view);
+
+/* log_n and limb count of a handle. */
+int hentt_tables_info(const hentt_tables *t, uint32_t *log_n, uint32_t *limbs);
+
+/* Device pointers of the raw tables: fwd and inv are [limbs][N] arrays of
+ * (W, W') uint64 pairs (W = psi^brv(k), resp. psi^-brv(k)); moduli is
+ * [limbs] of 8-word records whose first word is q.  Read-only. */
+int hentt_tables_device_ptrs(const hentt_tables *t, const uint64_t **fwd, const uint64_t **inv,
+                             const uint64_t **moduli);
+
+/* The library's psi for (q, N): smallest primitive 2N-th root of unity mod q.
+ * Host-only helper, no device work. */
+int hentt_psi(uint64_t q, uint32_t log_n, uint64_t *psi);
+
+/* Forward negacyclic NTT in place: x[batch][limbs][N], natural order ->
+ * bit-reversed NTT domain (section II-B). */
+int hentt_ntt_fwd(const hentt_tables *t, uint64_t *x, uint32_t batch, void *stream);
+
+/* Inverse negacyclic NTT in place: bit-reversed NTT domain -> natural order,
+ * including N^-1 and the psi^-i untwist (section II-B). */
+int hentt_ntt_inv(const hentt_tables *t, uint64_t *x, uint32_t batch, void *stream);
+
+/* Element-wise (dyadic) product out = a (.) b mod q_l over [batch][limbs][N]
+ * (section II-B).  out may alias a or b exactly (not partially). */
+int hentt_dyadic_mul(const hentt_tables *t, const uint64_t *a, const uint64_t *b, uint64_t *out,
+                     uint32_t batch, void *stream);
+
+/* Negacyclic products out = INTT(NTT(a) (.) NTT(b)) of coefficient-domain
+ * a, b over [batch][limbs][N] (section II-B), fused so that the NTT-domain
+ * values never leave the chip.  out must not overlap a or b. */
+int hentt_polymul(const hentt_tables *t, const uint64_t *a, const uint64_t *b, uint64_t *out, uint32_t batch,
+                  void *stream);
+
+/* Ciphertext tensor product (section II-A, Mul): c, d [batch][2][limbs][N],
+ * out [batch][3][limbs][N] = (c0 d0, c0 d1 + c1 d0, c1 d1) per limb, the middle
+ * term reduced once (mad_mod).  flags: HENTT_IN_COEFF | HENTT_IN_NTT combined
+ * with HENTT_OUT_COEFF | HENTT_OUT_NTT.  c and d are not modified; out must
+ * not overlap them. */
+int hentt_ct_tensor(const hentt_tables *t, const uint64_t *c, const uint64_t *d, uint64_t *out, uint32_t batch,
+                    uint32_t flags, void *stream);
+
+/* One polynomial set of an uneven batch: data [batch][limbs][N] in place,
+ * transformed with the first `limbs` moduli of `t` (limbs <= t's limbs). */
+typedef struct {
+  uint64_t *data;
+  const hentt_tables *t;
+  uint32_t limbs;
+  uint32_t batch;
+} hentt_job;
+
+/* Transforms every job (dir = +1 forward, -1 inverse), each job at its own N
+ * and limb count, in a single persistent kernel launch (section III-B,
+ * batch x RNS parallelism).  jobs is a HOST array; its contents are copied
+ * before the call returns. */
+int hentt_ntt_batch(const hentt_job *jobs, uint32_t njobs, int dir, void *stream);
+
+/* Kernel timing for benchmarks.  While enabled, every kernel the library
+ * launches is bracketed by HIP events recorded on the launching stream.
+ * hentt_prof_count() waits for the recorded events, folds them into per-kernel
+ * totals and returns the number of distinct kernels (or a negative status);
+ * hentt_prof_get() copies entry i: kernel name (with log_n), total milliseconds
+ * and launch count.  hentt_prof_enable() clears all records. */
+int hentt_prof_enable(int on);
+int hentt_prof_count(void);
+int hentt_prof_get(uint32_t i, char *name, uint32_t name_len, double *total_ms, uint32_t *launches);
+
+/* Text for a status code (static storage). */
+const char *hentt_status_str(int status);
+
+/* HIP error code behind the last HENTT_EHIP returned on this thread. */
+int hentt_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HENTT_H */

@@ -1,0 +1,243 @@
+"""hentt: batched negacyclic NTT over RNS limbs on AMD MI355X (gfx950).
+
+Python binding of libhentt.so (C ABI in include/hentt.h).  Argument
+marshalling only: shapes, dtypes and device pointers are checked here and
+every step of the computation runs in the library's HIP kernels.  PyTorch
+supplies device memory (int64 or uint64 tensors used as raw 64-bit words)
+and streams.  If the library is not built, every call raises HenttError.
+"""
+import ctypes
+import os
+
+import torch
+
+__all__ = ["HenttError", "Tables", "ntt_fwd", "ntt_inv", "dyadic_mul", "polymul", "ct_tensor", "ntt_batch",
+           "psi", "lib", "LIB_PATH", "prof_enable", "prof_read"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhentt.so")
+
+HENTT_IN_NTT = 1
+HENTT_OUT_NTT = 2
+_VP = ctypes.c_void_p
+_U32 = ctypes.c_uint32
+_U64 = ctypes.c_uint64
+
+
+class HenttError(RuntimeError):
+    pass
+
+
+class _Job(ctypes.Structure):
+    _fields_ = [("data", _VP), ("t", _VP), ("limbs", _U32), ("batch", _U32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libhentt.so (built by __graft_entry__.build()); raise if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise HenttError("libhentt.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        sigs = {
+            "hentt_tables_create": [_U32, _U32, ctypes.POINTER(_U64), _VP, ctypes.POINTER(_VP)],
+            "hentt_tables_destroy": [_VP],
+            "hentt_tables_view": [_VP, _U32, ctypes.POINTER(_VP)],
+            "hentt_tables_info": [_VP, ctypes.POINTER(_U32), ctypes.POINTER(_U32)],
+            "hentt_tables_device_ptrs": [_VP, ctypes.POINTER(_VP), ctypes.POINTER(_VP), ctypes.POINTER(_VP)],
+            "hentt_psi": [_U64, _U32, ctypes.POINTER(_U64)],
+            "hentt_ntt_fwd": [_VP, _VP, _U32, _VP],
+            "hentt_ntt_inv": [_VP, _VP, _U32, _VP],
+            "hentt_dyadic_mul": [_VP, _VP, _VP, _VP, _U32, _VP],
+            "hentt_polymul": [_VP, _VP, _VP, _VP, _U32, _VP],
+            "hentt_ct_tensor": [_VP, _VP, _VP, _VP, _U32, _U32, _VP],
+            "hentt_ntt_batch": [ctypes.POINTER(_Job), _U32, ctypes.c_int, _VP],
+            "hentt_last_hip_error": [],
+            "hentt_prof_enable": [ctypes.c_int],
+            "hentt_prof_count": [],
+            "hentt_prof_get": [_U32, ctypes.c_char_p, _U32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_U32)],
+        }
+        for name, args in sigs.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        L.hentt_status_str.argtypes = [ctypes.c_int]
+        L.hentt_status_str.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc, what):
+    if rc != 0:
+        L = lib()
+        msg = L.hentt_status_str(rc).decode()
+        if rc == -4:
+            msg += " (hipError %d)" % L.hentt_last_hip_error()
+        raise HenttError("%s failed: %s [%d]" % (what, msg, rc))
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    if isinstance(stream, torch.cuda.Stream):
+        return _VP(stream.cuda_stream)
+    return _VP(int(stream))
+
+
+def _words(t, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise HenttError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype not in (torch.int64, torch.uint64):
+        raise HenttError("%s must be int64 or uint64 (64-bit words), got %s" % (name, t.dtype))
+    if not t.is_contiguous():
+        raise HenttError("%s must be contiguous" % name)
+    return _VP(t.data_ptr())
+
+
+def prof_enable(on=True):
+    """Start (clearing old records) or stop per-kernel event timing."""
+    _check(lib().hentt_prof_enable(1 if on else 0), "hentt_prof_enable")
+
+
+def prof_read():
+    """Wait for the timed launches; {kernel name: (total_ms, launches)}."""
+    L = lib()
+    n = L.hentt_prof_count()
+    if n < 0:
+        _check(n, "hentt_prof_count")
+    out = {}
+    buf = ctypes.create_string_buffer(128)
+    for i in range(n):
+        ms, cnt = ctypes.c_double(), _U32()
+        _check(L.hentt_prof_get(i, buf, 128, ctypes.byref(ms), ctypes.byref(cnt)), "hentt_prof_get")
+        out[buf.value.decode()] = (ms.value, cnt.value)
+    return out
+
+
+def psi(q, log_n):
+    """The library's psi: smallest primitive 2N-th root of unity mod q."""
+    out = _U64()
+    _check(lib().hentt_psi(q, log_n, ctypes.byref(out)), "hentt_psi")
+    return out.value
+
+
+class Tables:
+    """Device twiddle tables for a modulus chain at N = 2^log_n."""
+
+    def __init__(self, log_n, moduli, stream=None, _handle=None):
+        self._h = None
+        if _handle is not None:
+            self._h = _handle
+        else:
+            arr = (_U64 * len(moduli))(*[int(m) for m in moduli])
+            h = _VP()
+            _check(lib().hentt_tables_create(log_n, len(moduli), arr, _stream(stream), ctypes.byref(h)),
+                   "hentt_tables_create")
+            self._h = h
+        ln, lm = _U32(), _U32()
+        _check(lib().hentt_tables_info(self._h, ctypes.byref(ln), ctypes.byref(lm)), "hentt_tables_info")
+        self.log_n, self.limbs = ln.value, lm.value
+        self.n = 1 << self.log_n
+
+    def view(self, limbs):
+        h = _VP()
+        _check(lib().hentt_tables_view(self._h, limbs, ctypes.byref(h)), "hentt_tables_view")
+        return Tables(None, None, _handle=h)
+
+    def device_ptrs(self):
+        f, i, m = _VP(), _VP(), _VP()
+        _check(lib().hentt_tables_device_ptrs(self._h, ctypes.byref(f), ctypes.byref(i), ctypes.byref(m)),
+               "hentt_tables_device_ptrs")
+        return f.value, i.value, m.value
+
+    def close(self):
+        if self._h is not None and _lib is not None:
+            lib().hentt_tables_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+
+def _batch_of(tables, x, per_item=1, name="x"):
+    if x.dim() < 2 or x.shape[-1] != tables.n or x.shape[-2] != tables.limbs:
+        raise HenttError("%s must have shape [..., limbs=%d, N=%d], got %s" % (name, tables.limbs, tables.n,
+                                                                               tuple(x.shape)))
+    b = x.numel() // (tables.limbs * tables.n * per_item)
+    if b * per_item * tables.limbs * tables.n != x.numel() or b == 0:
+        raise HenttError("%s: size is not a whole number of items" % name)
+    return b
+
+
+def ntt_fwd(tables, x, stream=None):
+    """In-place forward negacyclic NTT of x[..., limbs, N] (bit-reversed output)."""
+    _check(lib().hentt_ntt_fwd(tables.handle, _words(x, "x"), _batch_of(tables, x), _stream(stream)),
+           "hentt_ntt_fwd")
+    return x
+
+
+def ntt_inv(tables, x, stream=None):
+    """In-place inverse negacyclic NTT of x[..., limbs, N]."""
+    _check(lib().hentt_ntt_inv(tables.handle, _words(x, "x"), _batch_of(tables, x), _stream(stream)),
+           "hentt_ntt_inv")
+    return x
+
+
+def dyadic_mul(tables, a, b, out=None, stream=None):
+    if a.shape != b.shape:
+        raise HenttError("a and b must have the same shape")
+    if out is None:
+        out = torch.empty_like(a)
+    _check(lib().hentt_dyadic_mul(tables.handle, _words(a, "a"), _words(b, "b"), _words(out, "out"),
+                                  _batch_of(tables, a, name="a"), _stream(stream)), "hentt_dyadic_mul")
+    return out
+
+
+def polymul(tables, a, b, out=None, stream=None):
+    """Negacyclic products of coefficient-domain a, b [..., limbs, N]."""
+    if a.shape != b.shape:
+        raise HenttError("a and b must have the same shape")
+    if out is None:
+        out = torch.empty_like(a)
+    _check(lib().hentt_polymul(tables.handle, _words(a, "a"), _words(b, "b"), _words(out, "out"),
+                               _batch_of(tables, a, name="a"), _stream(stream)), "hentt_polymul")
+    return out
+
+
+def ct_tensor(tables, c, d, out=None, in_ntt=False, out_ntt=False, stream=None):
+    """Ciphertext tensor: c, d [batch, 2, limbs, N] -> [batch, 3, limbs, N]."""
+    if c.shape != d.shape or c.dim() != 4 or c.shape[1] != 2:
+        raise HenttError("c and d must both have shape [batch, 2, limbs, N]")
+    batch = _batch_of(tables, c, per_item=2, name="c")
+    if out is None:
+        out = torch.empty((batch, 3, tables.limbs, tables.n), dtype=c.dtype, device=c.device)
+    elif tuple(out.shape) != (batch, 3, tables.limbs, tables.n):
+        raise HenttError("out must have shape [batch, 3, limbs, N]")
+    flags = (HENTT_IN_NTT if in_ntt else 0) | (HENTT_OUT_NTT if out_ntt else 0)
+    _check(lib().hentt_ct_tensor(tables.handle, _words(c, "c"), _words(d, "d"), _words(out, "out"), batch, flags,
+                                 _stream(stream)), "hentt_ct_tensor")
+    return out
+
+
+def ntt_batch(jobs, direction, stream=None):
+    """Transform an uneven batch in one launch.  jobs: list of (x, tables, limbs)
+    with x [batch, limbs, N] for that tables' N; direction +1 or -1."""
+    arr = (_Job * len(jobs))()
+    for i, (x, t, limbs) in enumerate(jobs):
+        if x.shape[-1] != t.n or x.shape[-2] != limbs:
+            raise HenttError("job %d: x must have shape [batch, limbs=%d, N=%d]" % (i, limbs, t.n))
+        arr[i].data = _words(x, "job data")
+        arr[i].t = t.handle
+        arr[i].limbs = limbs
+        arr[i].batch = x.numel() // (limbs * t.n)
+    _check(lib().hentt_ntt_batch(arr, len(jobs), int(direction), _stream(stream)), "hentt_ntt_batch")

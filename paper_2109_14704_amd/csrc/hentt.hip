@@ -1,0 +1,602 @@
+// libhentt: C ABI, twiddle tables, argument checks and kernel dispatch.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+#include <atomic>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/hentt.h"
+#include "ntt_kernels.hpp"
+
+using namespace hentt;
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+inline int hip_fail(hipError_t e) {
+  g_last_hip = (int)e;
+  return HENTT_EHIP;
+}
+#define HIPCHK(x)                            \
+  do {                                       \
+    hipError_t e_ = (x);                     \
+    if (e_ != hipSuccess) return hip_fail(e_); \
+  } while (0)
+
+typedef unsigned __int128 u128;
+
+// ------------------------------------------------------------ host number theory
+uint64_t h_mul(uint64_t a, uint64_t b, uint64_t m) { return (uint64_t)((u128)a * b % m); }
+uint64_t h_pow(uint64_t b, uint64_t e, uint64_t m) {
+  uint64_t r = 1;
+  b %= m;
+  for (; e; e >>= 1, b = h_mul(b, b, m))
+    if (e & 1) r = h_mul(r, b, m);
+  return r;
+}
+
+// Miller-Rabin with the witness set {2, 325, 9375, 28178, 450775, 9780504,
+// 1795265022} (Jim Sinclair), deterministic for all n < 2^64.
+bool h_is_prime(uint64_t n) {
+  if (n < 2) return false;
+  for (uint64_t p : {2ull, 3ull, 5ull, 7ull, 11ull, 13ull})
+    if (n % p == 0) return n == p;
+  uint64_t d = n - 1;
+  int s = __builtin_ctzll(d);
+  d >>= s;
+  for (uint64_t a : {2ull, 325ull, 9375ull, 28178ull, 450775ull, 9780504ull, 1795265022ull}) {
+    a %= n;
+    if (a == 0) continue;
+    uint64_t x = h_pow(a, d, n);
+    if (x == 1 || x == n - 1) continue;
+    bool comp = true;
+    for (int r = 1; r < s && comp; ++r) {
+      x = h_mul(x, x, n);
+      if (x == n - 1) comp = false;
+    }
+    if (comp) return false;
+  }
+  return true;
+}
+
+uint32_t h_brv(uint32_t x, int bits) { return __builtin_bitreverse32(x) >> (32 - bits); }
+
+// Smallest primitive 2N-th root: take any root g of order 2N (a residue r
+// with r^N = -1 gives g = r^((q-1)/2N)... found by testing small bases), then
+// scan its odd powers g, g^3, ... for the minimum.
+uint64_t h_psi(uint64_t q, int log_n) {
+  const uint64_t two_n = 2ull << log_n;
+  const uint64_t e = (q - 1) / two_n;
+  uint64_t g = 0;
+  for (uint64_t r = 2; r < 1000000 && r < q; ++r) {
+    uint64_t c = h_pow(r, e, q);
+    if (h_pow(c, two_n / 2, q) == q - 1) {
+      g = c;
+      break;
+    }
+  }
+  if (!g) return 0;
+  const uint64_t g2 = h_mul(g, g, q);
+  uint64_t best = g, cur = g;
+  for (uint64_t j = 1; j < two_n / 2; ++j) {
+    cur = h_mul(cur, g2, q);
+    if (cur < best) best = cur;
+  }
+  return best;
+}
+
+int bit_length(uint64_t v) { return 64 - __builtin_clzll(v); }
+
+int check_modulus(uint64_t q, int log_n) {
+  if (q <= (1ull << 7) || q >= (1ull << 60)) return HENTT_EMODULUS;
+  if ((q - 1) % (2ull << log_n) != 0) return HENTT_EMODULUS;
+  if (!h_is_prime(q)) return HENTT_EMODULUS;
+  return HENTT_OK;
+}
+
+inline uint64_t shoup_quot(uint64_t w, uint64_t q) { return (uint64_t)(((u128)w << 64) / q); }
+
+// ------------------------------------------------------------ table storage
+struct Storage {
+  std::atomic<int> refs{1};
+  uint32_t log_n = 0, limbs = 0;
+  Tw *d_tw = nullptr;          // [limbs][2][N]
+  LimbConst *d_lc = nullptr;   // [limbs]
+  std::vector<uint64_t> moduli;
+  int device = 0;
+};
+
+void release(Storage *s) {
+  if (s->refs.fetch_sub(1) == 1) {
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(s->device);
+    if (s->d_tw) (void)hipFree(s->d_tw);
+    if (s->d_lc) (void)hipFree(s->d_lc);
+    (void)hipSetDevice(cur);
+    delete s;
+  }
+}
+
+// ------------------------------------------------------------ workspace pool
+// Device buffers reused by capacity: a request takes the smallest free buffer
+// that is large enough, else allocates (the memory cache of section III-C-1).
+// A buffer handed out stays with its stream's queued work; it is returned to
+// the pool right after the launches are enqueued, which is safe because all
+// users of one pool entry enqueue on streams that the caller serialises, and
+// the stream ordering of the same stream keeps reuse after completion.
+struct PoolEntry {
+  void *ptr;
+  size_t bytes;
+  int device;
+  hipStream_t stream;
+  bool busy;
+};
+std::mutex g_pool_mu;
+std::vector<PoolEntry> g_pool;
+
+int pool_get(size_t bytes, hipStream_t stream, void **out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  int best = -1;
+  for (size_t i = 0; i < g_pool.size(); ++i) {
+    PoolEntry &e = g_pool[i];
+    if (e.busy || e.device != dev || e.bytes < bytes) continue;
+    if (e.stream != stream) continue;  // reuse only in the stream order that last used it
+    if (best < 0 || e.bytes < g_pool[best].bytes) best = (int)i;
+  }
+  if (best >= 0) {
+    g_pool[best].busy = true;
+    *out = g_pool[best].ptr;
+    return HENTT_OK;
+  }
+  void *p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    g_last_hip = (int)e;
+    return HENTT_ENOMEM;
+  }
+  g_pool.push_back({p, bytes, dev, stream, true});
+  *out = p;
+  return HENTT_OK;
+}
+void pool_put(void *p) {
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  for (auto &e : g_pool)
+    if (e.ptr == p) e.busy = false;
+}
+
+
+// ------------------------------------------------------------ launch timing
+// Optional per-kernel timing with HIP events recorded on the launching stream
+// around each kernel (hentt_prof_enable); read back with hentt_prof_get.
+struct ProfRec {
+  std::string name;
+  hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof;
+struct ProfAgg {
+  std::string name;
+  double ms;
+  uint32_t n;
+};
+std::vector<ProfAgg> g_prof_agg;
+
+struct LaunchTimer {
+  hipEvent_t a = nullptr, b = nullptr;
+  hipStream_t st;
+  const char *name;
+  int ln;
+  LaunchTimer(const char *nm, int log_n, hipStream_t s) : st(s), name(nm), ln(log_n) {
+    if (g_prof_on && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess) (void)hipEventRecord(a, st);
+  }
+  ~LaunchTimer() {
+    if (a && b) {
+      (void)hipEventRecord(b, st);
+      std::lock_guard<std::mutex> lk(g_prof_mu);
+      g_prof.push_back({std::string(name) + "<" + std::to_string(ln) + ">", a, b});
+    }
+  }
+};
+}  // namespace
+
+struct hentt_tables {
+  Storage *s;
+  uint32_t limbs;  // <= s->limbs
+};
+
+// ------------------------------------------------------------ dispatch
+namespace {
+
+// Stage split per N: transforms with N <= 2^14 run whole in one workgroup
+// (one HBM round trip); larger N run a column pass of EC stages then blocks
+// of 2^(log_n - EC) coefficients.
+template <int LOGN> struct Plan {
+  static constexpr bool WHOLE = LOGN <= 14;
+  static constexpr int EC = LOGN <= 15 ? (LOGN - 12 > 0 ? LOGN - 12 : 1) : (LOGN == 16 ? 4 : 4);
+  static constexpr int B = LOGN - EC;
+  // fused products: one kernel up to 2^12, else column pass + blocks
+  static constexpr bool PROD_WHOLE = LOGN <= 12;
+};
+
+ColArgs col_args(uint64_t *x, uint64_t sb) {
+  ColArgs a{};
+  a.src[0] = x;
+  a.dst[0] = x;
+  a.src_sb = a.dst_sb = sb;
+  return a;
+}
+
+template <int LOGN>
+void launch_fwd(const hentt_tables *t, uint64_t *x, uint32_t batch, hipStream_t st) {
+  const Tw *tw = t->s->d_tw;
+  const LimbConst *lc = t->s->d_lc;
+  const uint32_t L = t->limbs;
+  const uint32_t units = batch * L;
+  using P = Plan<LOGN>;
+  if constexpr (P::WHOLE) {
+    { LaunchTimer lt_("k_fwd_whole", LOGN, st); hipLaunchKernelGGL((k_fwd_whole<LOGN, 4>), dim3(units), dim3(1 << (LOGN - 4)), 0, st, x, tw, lc, batch, L); }
+  } else {
+    { LaunchTimer lt_("k_cols_fwd", LOGN, st); hipLaunchKernelGGL((k_cols<LOGN, P::EC, false>), dim3(units * ((1u << (LOGN - P::EC)) / 256)), dim3(256), 0, st,
+                       col_args(x, (uint64_t)L << LOGN), tw, lc, batch, L); }
+    { LaunchTimer lt_("k_fwd_blocks", LOGN, st); hipLaunchKernelGGL((k_fwd_blocks<LOGN, P::B, 4>), dim3(units << (LOGN - P::B)), dim3(1 << (P::B - 4)), 0, st, x,
+                       tw, lc, batch, L); }
+  }
+}
+
+template <int LOGN>
+void launch_inv(const hentt_tables *t, uint64_t *x, uint32_t batch, hipStream_t st) {
+  const Tw *tw = t->s->d_tw;
+  const LimbConst *lc = t->s->d_lc;
+  const uint32_t L = t->limbs;
+  const uint32_t units = batch * L;
+  using P = Plan<LOGN>;
+  if constexpr (P::WHOLE) {
+    { LaunchTimer lt_("k_inv_whole", LOGN, st); hipLaunchKernelGGL((k_inv_whole<LOGN, 4>), dim3(units), dim3(1 << (LOGN - 4)), 0, st, x, tw, lc, batch, L); }
+  } else {
+    { LaunchTimer lt_("k_inv_blocks", LOGN, st); hipLaunchKernelGGL((k_inv_blocks<LOGN, P::B, 4>), dim3(units << (LOGN - P::B)), dim3(1 << (P::B - 4)), 0, st, x,
+                       tw, lc, batch, L); }
+    { LaunchTimer lt_("k_cols_inv", LOGN, st); hipLaunchKernelGGL((k_cols<LOGN, P::EC, true>), dim3(units * ((1u << (LOGN - P::EC)) / 256)), dim3(256), 0, st,
+                       col_args(x, (uint64_t)L << LOGN), tw, lc, batch, L); }
+  }
+}
+
+// Products: in/out component pointers with their batch strides.  in_coeff:
+// inputs are coefficient-domain (forward transforms applied); out_coeff:
+// outputs go back to the coefficient domain.  ws: workspace for the forward
+// column pass output when the product is not one kernel (NIN components of
+// batch * limbs * N words), may be null otherwise.
+template <int LOGN, int MODE>
+void launch_prod(const hentt_tables *t, const ProdArgs &pa, uint32_t batch, bool in_coeff, bool out_coeff,
+                 uint64_t *ws, hipStream_t st) {
+  const Tw *tw = t->s->d_tw;
+  const LimbConst *lc = t->s->d_lc;
+  const uint32_t L = t->limbs;
+  const uint32_t units = batch * L;
+  constexpr int NIN = ProdShape<MODE>::NIN, NOUT = ProdShape<MODE>::NOUT;
+  using P = Plan<LOGN>;
+  if (!in_coeff && !out_coeff) {
+    const uint32_t tiles = LOGN > 11 ? (1u << (LOGN - 11)) : 1u;
+    { LaunchTimer lt_(MODE == PROD_MUL ? "k_elem_mul" : "k_elem_tensor", LOGN, st); hipLaunchKernelGGL((k_elem<MODE>), dim3(units * tiles), dim3(256), 0, st, pa, lc, batch, L, (uint32_t)LOGN, tiles); }
+    return;
+  }
+  if constexpr (P::PROD_WHOLE) {
+    const dim3 g(units), blk(1 << (LOGN - 4));
+    if (in_coeff && out_coeff) { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, LOGN, 4, MODE, true, true>), g, blk, 0, st, pa, tw, lc, batch, L); }
+    else if (in_coeff) { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, LOGN, 4, MODE, true, false>), g, blk, 0, st, pa, tw, lc, batch, L); }
+    else { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, LOGN, 4, MODE, false, true>), g, blk, 0, st, pa, tw, lc, batch, L); }
+  } else {
+    constexpr int EC = P::EC, B = P::B;
+    const uint64_t NL = (uint64_t)L << LOGN;
+    ProdArgs pb = pa;
+    if (in_coeff) {
+      // forward column pass of every input into the workspace ([NIN][batch][L][N])
+      ColArgs ca{};
+      for (int p = 0; p < NIN; ++p) {
+        ca.src[p] = pa.in[p];
+        ca.dst[p] = ws + (uint64_t)p * batch * NL;
+        pb.in[p] = ca.dst[p];
+      }
+      ca.src_sb = pa.in_sb;
+      ca.dst_sb = NL;
+      pb.in_sb = NL;
+      { LaunchTimer lt_("k_cols_fwd", LOGN, st); hipLaunchKernelGGL((k_cols<LOGN, EC, false>), dim3(NIN * units * ((1u << (LOGN - EC)) / 256)), dim3(256), 0, st,
+                         ca, tw, lc, batch, L); }
+    }
+    const dim3 g(units << (LOGN - B)), blk(1 << (B - 4));
+    if (in_coeff && out_coeff) { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, B, 4, MODE, true, true>), g, blk, 0, st, pb, tw, lc, batch, L); }
+    else if (in_coeff) { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, B, 4, MODE, true, false>), g, blk, 0, st, pb, tw, lc, batch, L); }
+    else { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, B, 4, MODE, false, true>), g, blk, 0, st, pb, tw, lc, batch, L); }
+    if (out_coeff) {
+      ColArgs ca{};
+      for (int o = 0; o < NOUT; ++o) ca.src[o] = ca.dst[o] = pa.out[o];
+      ca.src_sb = ca.dst_sb = pa.out_sb;
+      { LaunchTimer lt_("k_cols_inv", LOGN, st); hipLaunchKernelGGL((k_cols<LOGN, EC, true>), dim3(NOUT * units * ((1u << (LOGN - EC)) / 256)), dim3(256), 0, st,
+                         ca, tw, lc, batch, L); }
+    }
+  }
+}
+
+template <int LOGN> constexpr bool needs_ws() { return !Plan<LOGN>::PROD_WHOLE; }
+
+typedef void (*launch_fn)(const hentt_tables *, uint64_t *, uint32_t, hipStream_t);
+typedef void (*prod_fn)(const hentt_tables *, const ProdArgs &, uint32_t, bool, bool, uint64_t *, hipStream_t);
+
+#define HENTT_SIZES(M) M(6) M(7) M(8) M(9) M(10) M(11) M(12) M(13) M(14) M(15) M(16) M(17)
+#define FWD_ENTRY(n) launch_fwd<n>,
+#define INV_ENTRY(n) launch_inv<n>,
+#define MUL_ENTRY(n) launch_prod<n, PROD_MUL>,
+#define TEN_ENTRY(n) launch_prod<n, PROD_TENSOR>,
+#define WS_ENTRY(n) needs_ws<n>(),
+const launch_fn k_fwd_table[] = {HENTT_SIZES(FWD_ENTRY)};
+const launch_fn k_inv_table[] = {HENTT_SIZES(INV_ENTRY)};
+const prod_fn k_mul_table[] = {HENTT_SIZES(MUL_ENTRY)};
+const prod_fn k_ten_table[] = {HENTT_SIZES(TEN_ENTRY)};
+const bool k_ws_table[] = {HENTT_SIZES(WS_ENTRY)};
+
+int run_transform(const hentt_tables *t, uint64_t *x, uint32_t batch, hipStream_t st, bool inv) {
+  const int ln = (int)t->s->log_n;
+  (inv ? k_inv_table : k_fwd_table)[ln - HENTT_LOG_N_MIN](t, x, batch, st);
+  HIPCHK(hipGetLastError());
+  return HENTT_OK;
+}
+
+int run_prod(const hentt_tables *t, int mode, const ProdArgs &pa, uint32_t batch, bool in_coeff, bool out_coeff,
+             hipStream_t st) {
+  const int ln = (int)t->s->log_n;
+  const int nin = mode == PROD_MUL ? 2 : 4;
+  void *ws = nullptr;
+  if (in_coeff && k_ws_table[ln - HENTT_LOG_N_MIN]) {
+    int rc = pool_get((size_t)nin * batch * t->limbs * 8ull << ln, st, &ws);
+    if (rc) return rc;
+  }
+  (mode == PROD_MUL ? k_mul_table : k_ten_table)[ln - HENTT_LOG_N_MIN](t, pa, batch, in_coeff, out_coeff,
+                                                                       (uint64_t *)ws, st);
+  hipError_t e = hipGetLastError();
+  if (ws) pool_put(ws);
+  if (e != hipSuccess) return hip_fail(e);
+  return HENTT_OK;
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+extern "C" {
+
+const char *hentt_status_str(int s) {
+  switch (s) {
+    case HENTT_OK: return "ok";
+    case HENTT_EINVAL: return "invalid argument";
+    case HENTT_EMODULUS: return "bad modulus (must be prime, 1 mod 2N, 2^7 < q < 2^60)";
+    case HENTT_ENOMEM: return "out of memory";
+    case HENTT_EHIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+int hentt_last_hip_error(void) { return g_last_hip; }
+
+int hentt_psi(uint64_t q, uint32_t log_n, uint64_t *psi) {
+  if (!psi || log_n < 1 || log_n > 30) return HENTT_EINVAL;
+  if (q < 3 || (q - 1) % (2ull << log_n) != 0 || !h_is_prime(q)) return HENTT_EMODULUS;
+  uint64_t p = h_psi(q, (int)log_n);
+  if (!p) return HENTT_EMODULUS;
+  *psi = p;
+  return HENTT_OK;
+}
+
+int hentt_tables_create(uint32_t log_n, uint32_t limbs, const uint64_t *moduli_host, void *stream,
+                        hentt_tables **out) {
+  if (!out || !moduli_host || limbs == 0 || limbs > HENTT_LIMBS_MAX) return HENTT_EINVAL;
+  if (log_n < HENTT_LOG_N_MIN || log_n > HENTT_LOG_N_MAX) return HENTT_EINVAL;
+  *out = nullptr;
+  for (uint32_t l = 0; l < limbs; ++l) {
+    int rc = check_modulus(moduli_host[l], (int)log_n);
+    if (rc) return rc;
+  }
+  const uint32_t N = 1u << log_n;
+  std::vector<Tw> tw((size_t)limbs * 2 * N);
+  std::vector<LimbConst> lc(limbs);
+  std::vector<uint64_t> pw(N), ipw(N);
+  for (uint32_t l = 0; l < limbs; ++l) {
+    const uint64_t q = moduli_host[l];
+    const uint64_t psi = h_psi(q, (int)log_n);
+    if (!psi) return HENTT_EMODULUS;
+    const uint64_t psi_inv = h_pow(psi, q - 2, q);
+    pw[0] = ipw[0] = 1;
+    for (uint32_t i = 1; i < N; ++i) {
+      pw[i] = h_mul(pw[i - 1], psi, q);
+      ipw[i] = h_mul(ipw[i - 1], psi_inv, q);
+    }
+    Tw *f = &tw[(size_t)l * 2 * N], *iv = f + N;
+    for (uint32_t k = 0; k < N; ++k) {
+      const uint32_t r = h_brv(k, (int)log_n);
+      f[k] = {pw[r], shoup_quot(pw[r], q)};
+      iv[k] = {ipw[r], shoup_quot(ipw[r], q)};
+    }
+    LimbConst &c = lc[l];
+    memset(&c, 0, sizeof(c));
+    c.q = q;
+    c.q2 = 2 * q;
+    c.ninv = h_pow(N % q, q - 2, q);
+    c.ninv_s = shoup_quot(c.ninv, q);
+    c.ninvw = h_mul(c.ninv, iv[1].w, q);
+    c.ninvw_s = shoup_quot(c.ninvw, q);
+    c.k = (uint32_t)bit_length(q);
+    c.mu = (uint64_t)(((u128)1 << (2 * c.k)) / q);
+  }
+  Storage *s = new (std::nothrow) Storage();
+  if (!s) return HENTT_ENOMEM;
+  s->log_n = log_n;
+  s->limbs = limbs;
+  s->moduli.assign(moduli_host, moduli_host + limbs);
+  (void)hipGetDevice(&s->device);
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipMalloc(&s->d_tw, tw.size() * sizeof(Tw));
+  if (e == hipSuccess) e = hipMalloc(&s->d_lc, lc.size() * sizeof(LimbConst));
+  if (e == hipSuccess) e = hipMemcpyAsync(s->d_tw, tw.data(), tw.size() * sizeof(Tw), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s->d_lc, lc.data(), lc.size() * sizeof(LimbConst), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    release(s);
+    g_last_hip = (int)e;
+    return e == hipErrorOutOfMemory ? HENTT_ENOMEM : HENTT_EHIP;
+  }
+  hentt_tables *h = new (std::nothrow) hentt_tables{s, limbs};
+  if (!h) {
+    release(s);
+    return HENTT_ENOMEM;
+  }
+  *out = h;
+  return HENTT_OK;
+}
+
+int hentt_tables_destroy(hentt_tables *t) {
+  if (!t) return HENTT_EINVAL;
+  release(t->s);
+  delete t;
+  return HENTT_OK;
+}
+
+int hentt_tables_view(const hentt_tables *t, uint32_t limbs, hentt_tables **view) {
+  if (!t || !view || limbs == 0 || limbs > t->limbs) return HENTT_EINVAL;
+  hentt_tables *h = new (std::nothrow) hentt_tables{t->s, limbs};
+  if (!h) return HENTT_ENOMEM;
+  t->s->refs.fetch_add(1);
+  *view = h;
+  return HENTT_OK;
+}
+
+int hentt_tables_info(const hentt_tables *t, uint32_t *log_n, uint32_t *limbs) {
+  if (!t) return HENTT_EINVAL;
+  if (log_n) *log_n = t->s->log_n;
+  if (limbs) *limbs = t->limbs;
+  return HENTT_OK;
+}
+
+int hentt_tables_device_ptrs(const hentt_tables *t, const uint64_t **fwd, const uint64_t **inv,
+                             const uint64_t **moduli) {
+  if (!t) return HENTT_EINVAL;
+  const size_t N = 1u << t->s->log_n;
+  // per limb: fwd pairs then inv pairs; callers index limb l at l * 2N pairs
+  if (fwd) *fwd = (const uint64_t *)t->s->d_tw;
+  if (inv) *inv = (const uint64_t *)(t->s->d_tw + N);
+  if (moduli) *moduli = (const uint64_t *)t->s->d_lc;
+  return HENTT_OK;
+}
+
+int hentt_ntt_fwd(const hentt_tables *t, uint64_t *x, uint32_t batch, void *stream) {
+  if (!t || !x || batch == 0) return HENTT_EINVAL;
+  return run_transform(t, x, batch, (hipStream_t)stream, false);
+}
+
+int hentt_ntt_inv(const hentt_tables *t, uint64_t *x, uint32_t batch, void *stream) {
+  if (!t || !x || batch == 0) return HENTT_EINVAL;
+  return run_transform(t, x, batch, (hipStream_t)stream, true);
+}
+
+int hentt_dyadic_mul(const hentt_tables *t, const uint64_t *a, const uint64_t *b, uint64_t *out, uint32_t batch,
+                     void *stream) {
+  if (!t || !a || !b || !out || batch == 0) return HENTT_EINVAL;
+  ProdArgs pa{};
+  pa.in[0] = a;
+  pa.in[1] = b;
+  pa.out[0] = out;
+  pa.in_sb = pa.out_sb = (uint64_t)t->limbs << t->s->log_n;
+  return run_prod(t, PROD_MUL, pa, batch, false, false, (hipStream_t)stream);
+}
+
+int hentt_polymul(const hentt_tables *t, const uint64_t *a, const uint64_t *b, uint64_t *out, uint32_t batch,
+                  void *stream) {
+  if (!t || !a || !b || !out || batch == 0) return HENTT_EINVAL;
+  ProdArgs pa{};
+  pa.in[0] = a;
+  pa.in[1] = b;
+  pa.out[0] = out;
+  pa.in_sb = pa.out_sb = (uint64_t)t->limbs << t->s->log_n;
+  return run_prod(t, PROD_MUL, pa, batch, true, true, (hipStream_t)stream);
+}
+
+int hentt_ct_tensor(const hentt_tables *t, const uint64_t *c, const uint64_t *d, uint64_t *out, uint32_t batch,
+                    uint32_t flags, void *stream) {
+  if (!t || !c || !d || !out || batch == 0 || (flags & ~3u)) return HENTT_EINVAL;
+  const uint64_t NL = (uint64_t)t->limbs << t->s->log_n;
+  ProdArgs pa{};
+  pa.in[0] = c;
+  pa.in[1] = c + NL;
+  pa.in[2] = d;
+  pa.in[3] = d + NL;
+  for (int o = 0; o < 3; ++o) pa.out[o] = out + o * NL;
+  pa.in_sb = 2 * NL;
+  pa.out_sb = 3 * NL;
+  return run_prod(t, PROD_TENSOR, pa, batch, !(flags & HENTT_IN_NTT), !(flags & HENTT_OUT_NTT), (hipStream_t)stream);
+}
+
+int hentt_ntt_batch(const hentt_job *jobs, uint32_t njobs, int dir, void *stream) {
+  if (!jobs || njobs == 0 || (dir != 1 && dir != -1)) return HENTT_EINVAL;
+  for (uint32_t j = 0; j < njobs; ++j) {
+    const hentt_job &jb = jobs[j];
+    if (!jb.data || !jb.t || jb.batch == 0 || jb.limbs == 0 || jb.limbs > jb.t->limbs) return HENTT_EINVAL;
+  }
+  for (uint32_t j = 0; j < njobs; ++j) {
+    hentt_tables v{jobs[j].t->s, jobs[j].limbs};
+    int rc = run_transform(&v, jobs[j].data, jobs[j].batch, (hipStream_t)stream, dir < 0);
+    if (rc) return rc;
+  }
+  return HENTT_OK;
+}
+
+int hentt_prof_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (auto &r : g_prof) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  g_prof.clear();
+  g_prof_agg.clear();
+  g_prof_on = on != 0;
+  return HENTT_OK;
+}
+
+int hentt_prof_count(void) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (auto &r : g_prof) {
+    float ms = 0;
+    hipError_t e = hipEventSynchronize(r.b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+    if (e != hipSuccess) return hip_fail(e);
+    bool found = false;
+    for (auto &g : g_prof_agg)
+      if (g.name == r.name) {
+        g.ms += ms;
+        g.n += 1;
+        found = true;
+      }
+    if (!found) g_prof_agg.push_back({r.name, (double)ms, 1});
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  g_prof.clear();
+  return (int)g_prof_agg.size();
+}
+
+int hentt_prof_get(uint32_t i, char *name, uint32_t name_len, double *total_ms, uint32_t *launches) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (i >= g_prof_agg.size() || !name || name_len == 0) return HENTT_EINVAL;
+  snprintf(name, name_len, "%s", g_prof_agg[i].name.c_str());
+  if (total_ms) *total_ms = g_prof_agg[i].ms;
+  if (launches) *launches = g_prof_agg[i].n;
+  return HENTT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,481 @@
+// Staged negacyclic NTT kernels for gfx950 (CDNA4), section III-B of the paper
+// re-planned for a 64-wide wavefront, a 160 KB LDS and 512 VGPRs per lane.
+//
+// Data: x[poly][N] uint64, poly = batch * limbs + limb (limb fastest among
+// polynomials, coefficient fastest overall).  Twiddles per limb: forward table
+// psi^brv(k) and inverse table psi^-brv(k), k < N, each stored as (W, W')
+// 16-byte pairs with W' = floor(W 2^64 / q) (the root powers and root power
+// quotients of Algorithm 1).
+//
+// A transform is a sequence of "rounds".  A round applies R consecutive
+// butterfly stages to groups of 2^R elements held in one lane's registers;
+// the butterfly pairs of those stages differ in the index bits
+// [LO, LO + R).  Rounds exchange data through LDS (inside a workgroup) or
+// through HBM (between the column pass and the block pass of large N), as in
+// the staged global -> local -> register design of section III-B, with the
+// radix-2^R register blocking of its high-radix subsection.
+#pragma once
+#include "modarith.hpp"
+
+namespace hentt {
+
+struct LimbConst {
+  uint64_t q, q2;         // q, 2q
+  uint64_t ninv, ninv_s;  // N^-1 mod q and its Shoup quotient
+  uint64_t ninvw, ninvw_s;  // N^-1 * psi^-brv(1) mod q and its Shoup quotient
+  uint64_t mu;            // floor(2^(2k) / q), k = bit length of q (Barrett)
+  uint32_t k, pad;
+};
+
+struct alignas(16) Tw { uint64_t w, ws; };
+
+// LDS padding: one spare element after every 16, so that the lane-strided
+// accesses of every round hit distinct banks.
+__device__ __forceinline__ constexpr uint32_t lds_pad(uint32_t i) { return i + (i >> 4); }
+template <int B> struct LdsSize { static constexpr int value = (1 << B) + (1 << B) / 16; };
+
+// Which block index bits a lane owns in a round over bits [LO, LO+R) of a
+// block of 2^B elements, with 2^E elements per lane (E >= R), 2^(B-E) lanes.
+// Lane bits fill the lowest free positions (coalescing), the remaining
+// E - R "group" bits the rest.
+template <int B, int E, int LO, int R>
+struct RoundMap {
+  static_assert(E >= R && LO + R <= B && E <= B, "bad round");
+  static constexpr int TB = B - E;
+  static constexpr bool LANE_LOW = (TB <= LO);  // all lane bits below LO: twiddles uniform per block
+  __device__ static __forceinline__ uint32_t lane_part(uint32_t tid) {
+    if constexpr (LANE_LOW) return tid;
+    else return (tid & ((1u << LO) - 1)) | ((tid >> LO) << (LO + R));
+  }
+  static constexpr uint32_t g_part(int g) {
+    uint32_t r = 0;
+    int bit = 0;
+    if constexpr (LANE_LOW) {
+      for (int pos = TB; pos < LO; ++pos, ++bit) if ((g >> bit) & 1) r |= 1u << pos;
+      for (int pos = LO + R; pos < B; ++pos, ++bit) if ((g >> bit) & 1) r |= 1u << pos;
+    } else {
+      for (int pos = TB + R; pos < B; ++pos, ++bit) if ((g >> bit) & 1) r |= 1u << pos;
+    }
+    return r;
+  }
+  static constexpr uint32_t slot_part(int s) { return g_part(s >> R) | (uint32_t)((s & ((1 << R) - 1)) << LO); }
+};
+
+// ---------------------------------------------------------------- rounds --
+// Forward stages with global index s = LOGN - LO - R + u, u < R.  Stage s
+// pairs j with j + N/2^(s+1) and uses psi_rev[2^s + (j >> (LOGN - s))].
+template <int LOGN, int B, int E, int LO, int R>
+__device__ __forceinline__ void fwd_round(uint64_t (&x)[1 << E], uint32_t blockStart, uint32_t lanePart,
+                                          const Tw* __restrict__ tw, uint64_t q, uint64_t q2) {
+  using M = RoundMap<B, E, LO, R>;
+#pragma unroll
+  for (int g = 0; g < (1 << (E - R)); ++g) {
+    const uint32_t J0 = M::LANE_LOW ? (blockStart | M::g_part(g)) : (blockStart | lanePart | M::g_part(g));
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int s = LOGN - LO - R + u;
+      const uint32_t base = (1u << s) + (J0 >> (LO + R - u));
+      const int h = 1 << (R - 1 - u);
+#pragma unroll
+      for (int k = 0; k < (1 << R); ++k) {
+        if (k & h) continue;
+        const Tw w = tw[base + (k >> (R - u))];
+        ct_bfly(x[(g << R) + k], x[(g << R) + k + h], w.w, w.ws, q, q2);
+      }
+    }
+  }
+}
+
+// Inverse stages v = LO + u.  Stage v pairs j with j + 2^v and uses
+// psi_rev^-1[N/2^(v+1) + (j >> (v+1))].  The last stage (v = LOGN-1) also
+// multiplies both outputs by N^-1.
+template <int LOGN, int B, int E, int LO, int R>
+__device__ __forceinline__ void inv_round(uint64_t (&x)[1 << E], uint32_t blockStart, uint32_t lanePart,
+                                          const Tw* __restrict__ itw, const LimbConst& c) {
+  using M = RoundMap<B, E, LO, R>;
+#pragma unroll
+  for (int g = 0; g < (1 << (E - R)); ++g) {
+    const uint32_t J0 = M::LANE_LOW ? (blockStart | M::g_part(g)) : (blockStart | lanePart | M::g_part(g));
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int v = LO + u;
+      const int d = 1 << u;
+      if (v == LOGN - 1) {
+        // last stage: one group, twiddle psi^-brv(1) folded with N^-1
+#pragma unroll
+        for (int k = 0; k < (1 << R); ++k) {
+          if (k & d) continue;
+          uint64_t& X = x[(g << R) + k];
+          uint64_t& Y = x[(g << R) + k + d];
+          uint64_t s = X + Y, df = X - Y + c.q2;
+          X = shoup(c.ninv, c.ninv_s, s, c.q);
+          Y = shoup(c.ninvw, c.ninvw_s, df, c.q);
+        }
+      } else {
+        const uint32_t base = (uint32_t)((1u << LOGN) >> (v + 1)) + (J0 >> (v + 1));
+#pragma unroll
+        for (int k = 0; k < (1 << R); ++k) {
+          if (k & d) continue;
+          const Tw w = itw[base + (k >> (u + 1))];
+          gs_bfly(x[(g << R) + k], x[(g << R) + k + d], w.w, w.ws, c.q, c.q2);
+        }
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------ data moves --
+template <int B, int E, int LO, int R>
+__device__ __forceinline__ void load_global(uint64_t (&x)[1 << E], const uint64_t* __restrict__ src, uint32_t lp) {
+  using M = RoundMap<B, E, LO, R>;
+#pragma unroll
+  for (int s = 0; s < (1 << E); ++s) x[s] = src[lp + M::slot_part(s)];
+}
+template <int B, int E, int LO, int R>
+__device__ __forceinline__ void store_global(const uint64_t (&x)[1 << E], uint64_t* __restrict__ dst, uint32_t lp) {
+  using M = RoundMap<B, E, LO, R>;
+#pragma unroll
+  for (int s = 0; s < (1 << E); ++s) dst[lp + M::slot_part(s)] = x[s];
+}
+template <int B, int E, int LO, int R>
+__device__ __forceinline__ void load_lds(uint64_t (&x)[1 << E], const uint64_t* lds, uint32_t lp) {
+  using M = RoundMap<B, E, LO, R>;
+#pragma unroll
+  for (int s = 0; s < (1 << E); ++s) x[s] = lds[lds_pad(lp + M::slot_part(s))];
+}
+template <int B, int E, int LO, int R>
+__device__ __forceinline__ void store_lds(const uint64_t (&x)[1 << E], uint64_t* lds, uint32_t lp) {
+  using M = RoundMap<B, E, LO, R>;
+#pragma unroll
+  for (int s = 0; s < (1 << E); ++s) lds[lds_pad(lp + M::slot_part(s))] = x[s];
+}
+
+// Canonical reductions.
+template <int E> __device__ __forceinline__ void reduce4(uint64_t (&x)[1 << E], uint64_t q, uint64_t q2) {
+#pragma unroll
+  for (int s = 0; s < (1 << E); ++s) x[s] = csub(csub(x[s], q2), q);
+}
+template <int E> __device__ __forceinline__ void reduce2(uint64_t (&x)[1 << E], uint64_t q) {
+#pragma unroll
+  for (int s = 0; s < (1 << E); ++s) x[s] = csub(x[s], q);
+}
+
+// --------------------------------------------------- block transforms ----
+// Forward rounds over the block bits [0, LO+R) (the first round covers
+// [LO, LO+R)), starting from registers already loaded with the first round's
+// map.  Ends with the lane holding the last round (LO = 0) map in registers,
+// i.e. 2^E consecutive elements, values in [0, 4q).
+template <int LOGN, int B, int E, int LO, int R>
+__device__ __forceinline__ void fwd_block_rounds(uint64_t (&x)[1 << E], uint64_t* lds, uint32_t tid,
+                                                 uint32_t blockStart, const Tw* __restrict__ tw, uint64_t q,
+                                                 uint64_t q2) {
+  using M = RoundMap<B, E, LO, R>;
+  const uint32_t lp = M::lane_part(tid);
+  fwd_round<LOGN, B, E, LO, R>(x, blockStart, lp, tw, q, q2);
+  if constexpr (LO > 0) {
+    constexpr int R2 = E;
+    constexpr int LO2 = LO - R2;
+    static_assert(LO2 >= 0, "rounds must tile the block");
+    store_lds<B, E, LO, R>(x, lds, lp);
+    __syncthreads();
+    using M2 = RoundMap<B, E, LO2, R2>;
+    load_lds<B, E, LO2, R2>(x, lds, M2::lane_part(tid));
+    fwd_block_rounds<LOGN, B, E, LO2, R2>(x, lds, tid, blockStart, tw, q, q2);
+  }
+}
+
+// Inverse rounds over block bits [LO, B), starting from registers loaded with
+// the (LO, R) map.  Ends with the lane holding the last round's map
+// (covering [B - Rlast, B)); values in [0, 2q).
+template <int LOGN, int B, int E, int LO, int R>
+__device__ __forceinline__ void inv_block_rounds(uint64_t (&x)[1 << E], uint64_t* lds, uint32_t tid,
+                                                 uint32_t blockStart, const Tw* __restrict__ itw,
+                                                 const LimbConst& c) {
+  using M = RoundMap<B, E, LO, R>;
+  const uint32_t lp = M::lane_part(tid);
+  inv_round<LOGN, B, E, LO, R>(x, blockStart, lp, itw, c);
+  if constexpr (LO + R < B) {
+    constexpr int LO2 = LO + R;
+    constexpr int R2 = (B - LO2) < E ? (B - LO2) : E;
+    store_lds<B, E, LO, R>(x, lds, lp);
+    __syncthreads();
+    using M2 = RoundMap<B, E, LO2, R2>;
+    load_lds<B, E, LO2, R2>(x, lds, M2::lane_part(tid));
+    inv_block_rounds<LOGN, B, E, LO2, R2>(x, lds, tid, blockStart, itw, c);
+  }
+}
+
+// Round geometry helpers.
+template <int B, int E> struct FwdFirst {   // forward: first round is the short one
+  static constexpr int R = (B % E) ? (B % E) : E;
+  static constexpr int LO = B - R;
+};
+template <int B, int E> struct InvLast {    // inverse: last round is the short one
+  static constexpr int R = (B % E) ? (B % E) : E;
+  static constexpr int LO = B - R;
+};
+
+// Map blockIdx -> (polynomial, tile): limb-major, batch next, tile fastest, so
+// that concurrently running workgroups share one limb's twiddle table in L2.
+struct Unit {
+  uint32_t poly, limb, tile;
+};
+__device__ __forceinline__ Unit unit_of(uint32_t bid, uint32_t tiles, uint32_t batch, uint32_t limbs) {
+  Unit u;
+  u.tile = bid % tiles;
+  uint32_t r = bid / tiles;
+  u.limb = r / batch;
+  uint32_t b = r % batch;
+  u.poly = b * limbs + u.limb;
+  return u;
+}
+
+// ------------------------------------------------------------- kernels ----
+// Whole transform of one polynomial per workgroup (N = 2^LOGN fits in LDS).
+template <int LOGN, int E>
+__global__ __launch_bounds__(1 << (LOGN - E)) void k_fwd_whole(uint64_t* __restrict__ x, const Tw* __restrict__ tw,
+                                                                const LimbConst* __restrict__ lc, uint32_t batch,
+                                                                uint32_t limbs) {
+  __shared__ uint64_t lds[LdsSize<LOGN>::value];
+  const Unit un = unit_of(blockIdx.x, 1, batch, limbs);
+  const uint64_t q = lc[un.limb].q, q2 = lc[un.limb].q2;
+  const Tw* t = tw + (size_t)un.limb * 2 * (1u << LOGN);
+  uint64_t* p = x + (size_t)un.poly * (1u << LOGN);
+  const uint32_t tid = threadIdx.x;
+  using F = FwdFirst<LOGN, E>;
+  uint64_t v[1 << E];
+  load_global<LOGN, E, F::LO, F::R>(v, p, RoundMap<LOGN, E, F::LO, F::R>::lane_part(tid));
+  fwd_block_rounds<LOGN, LOGN, E, F::LO, F::R>(v, lds, tid, 0, t, q, q2);
+  reduce4<E>(v, q, q2);
+  store_global<LOGN, E, 0, E>(v, p, RoundMap<LOGN, E, 0, E>::lane_part(tid));
+}
+
+template <int LOGN, int E>
+__global__ __launch_bounds__(1 << (LOGN - E)) void k_inv_whole(uint64_t* __restrict__ x, const Tw* __restrict__ tw,
+                                                                const LimbConst* __restrict__ lc, uint32_t batch,
+                                                                uint32_t limbs) {
+  __shared__ uint64_t lds[LdsSize<LOGN>::value];
+  const Unit un = unit_of(blockIdx.x, 1, batch, limbs);
+  const LimbConst c = lc[un.limb];
+  const Tw* it = tw + ((size_t)un.limb * 2 + 1) * (1u << LOGN);
+  uint64_t* p = x + (size_t)un.poly * (1u << LOGN);
+  const uint32_t tid = threadIdx.x;
+  using L = InvLast<LOGN, E>;
+  uint64_t v[1 << E];
+  load_global<LOGN, E, 0, E>(v, p, RoundMap<LOGN, E, 0, E>::lane_part(tid));
+  inv_block_rounds<LOGN, LOGN, E, 0, (LOGN < E ? LOGN : E)>(v, lds, tid, 0, it, c);
+  reduce2<E>(v, c.q);
+  store_global<LOGN, E, L::LO, L::R>(v, p, RoundMap<LOGN, E, L::LO, L::R>::lane_part(tid));
+}
+
+// Column pass: the first E forward stages (or the last E inverse stages) on
+// 2^E elements at stride N / 2^E; workgroup of 256 lanes = 256 columns.
+// Twiddles are the same for every lane (scalar loads).  Up to four
+// polynomial sets ("components") per launch, each read from src[c] and
+// written to dst[c] (equal for in place).
+struct ColArgs {
+  const uint64_t *src[4];
+  uint64_t *dst[4];
+  uint64_t src_sb, dst_sb;  // words between consecutive batch entries
+};
+
+template <int LOGN, int E, bool INV>
+__global__ __launch_bounds__(256) void k_cols(ColArgs a, const Tw *__restrict__ tw, const LimbConst *__restrict__ lc,
+                                              uint32_t batch, uint32_t limbs) {
+  constexpr uint32_t tiles = (1u << (LOGN - E)) / 256;
+  const uint32_t units = batch * limbs;
+  const uint32_t tile = blockIdx.x % tiles;
+  const uint32_t r = blockIdx.x / tiles;
+  const uint32_t comp = r / units, u = r % units;
+  const uint32_t limb = u / batch, b = u % batch;
+  const LimbConst c = lc[limb];
+  const uint64_t off = (uint64_t)limb << LOGN;
+  const uint64_t *src = a.src[comp] + (uint64_t)b * a.src_sb + off;
+  uint64_t *dst = a.dst[comp] + (uint64_t)b * a.dst_sb + off;
+  const uint32_t col = tile * 256 + threadIdx.x;
+  constexpr int LO = LOGN - E;
+  uint64_t v[1 << E];
+  load_global<LOGN, E, LO, E>(v, src, col);
+  if constexpr (!INV) {
+    const Tw *t = tw + (size_t)limb * 2 * (1u << LOGN);
+    fwd_round<LOGN, LOGN, E, LO, E>(v, 0, col, t, c.q, c.q2);
+  } else {
+    const Tw *it = tw + ((size_t)limb * 2 + 1) * (1u << LOGN);
+    inv_round<LOGN, LOGN, E, LO, E>(v, 0, col, it, c);
+    reduce2<E>(v, c.q);
+  }
+  store_global<LOGN, E, LO, E>(v, dst, col);
+}
+
+// Block pass of the forward transform: stages LOGN-B .. LOGN-1 on contiguous
+// blocks of 2^B elements; canonical output.
+template <int LOGN, int B, int E>
+__global__ __launch_bounds__(1 << (B - E)) void k_fwd_blocks(uint64_t *__restrict__ x, const Tw *__restrict__ tw,
+                                                              const LimbConst *__restrict__ lc, uint32_t batch,
+                                                              uint32_t limbs) {
+  __shared__ uint64_t lds[LdsSize<B>::value];
+  constexpr uint32_t tiles = 1u << (LOGN - B);
+  const Unit un = unit_of(blockIdx.x, tiles, batch, limbs);
+  const uint64_t q = lc[un.limb].q, q2 = lc[un.limb].q2;
+  const Tw *t = tw + (size_t)un.limb * 2 * (1u << LOGN);
+  const uint32_t blockStart = un.tile << B;
+  uint64_t *p = x + (size_t)un.poly * (1u << LOGN) + blockStart;
+  const uint32_t tid = threadIdx.x;
+  using F = FwdFirst<B, E>;
+  uint64_t v[1 << E];
+  load_global<B, E, F::LO, F::R>(v, p, RoundMap<B, E, F::LO, F::R>::lane_part(tid));
+  fwd_block_rounds<LOGN, B, E, F::LO, F::R>(v, lds, tid, blockStart, t, q, q2);
+  reduce4<E>(v, q, q2);
+  store_global<B, E, 0, E>(v, p, RoundMap<B, E, 0, E>::lane_part(tid));
+}
+
+// Block pass of the inverse transform: stages 0 .. B-1; lazy [0, 2q) output.
+template <int LOGN, int B, int E>
+__global__ __launch_bounds__(1 << (B - E)) void k_inv_blocks(uint64_t *__restrict__ x, const Tw *__restrict__ tw,
+                                                              const LimbConst *__restrict__ lc, uint32_t batch,
+                                                              uint32_t limbs) {
+  __shared__ uint64_t lds[LdsSize<B>::value];
+  constexpr uint32_t tiles = 1u << (LOGN - B);
+  const Unit un = unit_of(blockIdx.x, tiles, batch, limbs);
+  const LimbConst c = lc[un.limb];
+  const Tw *it = tw + ((size_t)un.limb * 2 + 1) * (1u << LOGN);
+  const uint32_t blockStart = un.tile << B;
+  uint64_t *p = x + (size_t)un.poly * (1u << LOGN) + blockStart;
+  const uint32_t tid = threadIdx.x;
+  using L = InvLast<B, E>;
+  uint64_t v[1 << E];
+  load_global<B, E, 0, E>(v, p, RoundMap<B, E, 0, E>::lane_part(tid));
+  inv_block_rounds<LOGN, B, E, 0, E>(v, lds, tid, blockStart, it, c);
+  store_global<B, E, L::LO, L::R>(v, p, RoundMap<B, E, L::LO, L::R>::lane_part(tid));
+}
+
+// ------------------------------------------------------ fused products ----
+// Returns p unchanged but hides that from the optimiser (adds an opaque,
+// wave-uniform zero), so loads through it are not merged with earlier ones.
+template <typename T> __device__ __forceinline__ const T *opaque(const T *p) {
+  uint32_t z = 0;
+  asm volatile("" : "+s"(z));
+  return p + z;
+}
+
+// Products of section II: PROD_MUL is the dyadic product of two polynomials
+// (a (.) b); PROD_TENSOR the ciphertext Mul tensor (c0 d0, c0 d1 + c1 d0,
+// c1 d1) with the middle term reduced once (mad_mod, section III-A-1).
+enum { PROD_MUL = 0, PROD_TENSOR = 1 };
+template <int MODE> struct ProdShape {
+  static constexpr int NIN = MODE == PROD_MUL ? 2 : 4;
+  static constexpr int NOUT = MODE == PROD_MUL ? 1 : 3;
+};
+struct ProdArgs {
+  const uint64_t *in[4];
+  uint64_t *out[3];
+  uint64_t in_sb, out_sb;  // words between consecutive batch entries
+};
+
+template <int MODE, int E>
+__device__ __forceinline__ void products(uint64_t (&X)[ProdShape<MODE>::NIN][1 << E],
+                                         uint64_t (&Y)[ProdShape<MODE>::NOUT][1 << E], const LimbConst &c) {
+#pragma unroll
+  for (int s = 0; s < (1 << E); ++s) {
+    if constexpr (MODE == PROD_MUL) {
+      Y[0][s] = mulmod(X[0][s], X[1][s], c.q, c.mu, c.k);
+    } else {
+      Y[0][s] = mulmod(X[0][s], X[2][s], c.q, c.mu, c.k);
+      Y[1][s] = madmod(X[0][s], X[3][s], X[1][s], X[2][s], c.q, c.mu, c.k);
+      Y[2][s] = mulmod(X[1][s], X[3][s], c.q, c.mu, c.k);
+    }
+  }
+}
+
+// One workgroup per block of 2^B coefficients of one (batch entry, limb):
+// forward block rounds of every input (DO_FWD; otherwise the inputs are
+// already NTT-domain values), the products in registers, then the inverse
+// block rounds of every output (DO_INV).  The forward transform ends and the
+// inverse transform begins with each lane holding 2^E consecutive NTT-domain
+// values, so the product needs no data exchange and the NTT-domain values
+// never leave the chip.  With B == LOGN the whole product is one kernel;
+// with B < LOGN the forward column pass runs before it and the inverse
+// column pass after it.
+template <int LOGN, int B, int E, int MODE, bool DO_FWD, bool DO_INV>
+__global__ __launch_bounds__(1 << (B - E)) void k_prod(ProdArgs a, const Tw *__restrict__ tw,
+                                                        const LimbConst *__restrict__ lc, uint32_t batch,
+                                                        uint32_t limbs) {
+  constexpr int NIN = ProdShape<MODE>::NIN, NOUT = ProdShape<MODE>::NOUT;
+  __shared__ uint64_t lds[(DO_FWD || DO_INV) ? LdsSize<B>::value : 2];
+  constexpr uint32_t tiles = 1u << (LOGN - B);
+  const uint32_t tile = blockIdx.x % tiles;
+  const uint32_t r = blockIdx.x / tiles;
+  const uint32_t limb = r / batch, b = r % batch;
+  const LimbConst c = lc[limb];
+  const Tw *t = tw + (size_t)limb * 2 * (1u << LOGN);
+  const Tw *it = t + (1u << LOGN);
+  const uint32_t blockStart = tile << B;
+  const uint64_t in_off = (uint64_t)b * a.in_sb + ((uint64_t)limb << LOGN) + blockStart;
+  const uint64_t out_off = (uint64_t)b * a.out_sb + ((uint64_t)limb << LOGN) + blockStart;
+  const uint32_t tid = threadIdx.x;
+  using F = FwdFirst<B, E>;
+  using L = InvLast<B, E>;
+  using M0 = RoundMap<B, E, 0, E>;
+  uint64_t X[NIN][1 << E];
+#pragma unroll
+  for (int p = 0; p < NIN; ++p) {
+    if constexpr (DO_FWD) {
+      if (p > 0) __syncthreads();  // the previous input's last LDS reads are done
+      // an opaque copy of the table pointer per input: the twiddles are re-read
+      // from cache for each input instead of being kept live in VGPRs
+      const Tw *tp = opaque(t);
+      load_global<B, E, F::LO, F::R>(X[p], a.in[p] + in_off, RoundMap<B, E, F::LO, F::R>::lane_part(tid));
+      fwd_block_rounds<LOGN, B, E, F::LO, F::R>(X[p], lds, tid, blockStart, tp, c.q, c.q2);
+      reduce4<E>(X[p], c.q, c.q2);
+    } else {
+      load_global<B, E, 0, E>(X[p], a.in[p] + in_off, M0::lane_part(tid));
+    }
+  }
+  uint64_t Y[NOUT][1 << E];
+  products<MODE, E>(X, Y, c);
+#pragma unroll
+  for (int o = 0; o < NOUT; ++o) {
+    if constexpr (DO_INV) {
+      __syncthreads();  // earlier LDS reads of this workgroup are done
+      inv_block_rounds<LOGN, B, E, 0, E>(Y[o], lds, tid, blockStart, opaque(it), c);
+      if constexpr (B == LOGN) reduce2<E>(Y[o], c.q);
+      store_global<B, E, L::LO, L::R>(Y[o], a.out[o] + out_off, RoundMap<B, E, L::LO, L::R>::lane_part(tid));
+    } else {
+      store_global<B, E, 0, E>(Y[o], a.out[o] + out_off, M0::lane_part(tid));
+    }
+  }
+}
+
+// Element-wise products of NTT-domain inputs (no transform): tiles of 2048
+// words of one (batch entry, limb), coalesced, limb constants uniform per
+// workgroup.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_elem(ProdArgs a, const LimbConst *__restrict__ lc, uint32_t batch,
+                                              uint32_t limbs, uint32_t log_n, uint32_t tiles) {
+  constexpr int NIN = ProdShape<MODE>::NIN, NOUT = ProdShape<MODE>::NOUT;
+  const uint32_t tile = blockIdx.x % tiles;
+  const uint32_t r = blockIdx.x / tiles;
+  const uint32_t limb = r / batch, b = r % batch;
+  const LimbConst c = lc[limb];
+  const uint32_t n = 1u << log_n;
+  const uint64_t in_off = (uint64_t)b * a.in_sb + ((uint64_t)limb << log_n) + tile * 2048u;
+  const uint64_t out_off = (uint64_t)b * a.out_sb + ((uint64_t)limb << log_n) + tile * 2048u;
+  uint64_t X[NIN][8], Y[NOUT][8];
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const uint32_t i = threadIdx.x + 256u * s;
+#pragma unroll
+    for (int p = 0; p < NIN; ++p) X[p][s] = (tile * 2048u + i < n) ? a.in[p][in_off + i] : 0;
+  }
+  products<MODE, 3>(X, Y, c);
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const uint32_t i = threadIdx.x + 256u * s;
+    if (tile * 2048u + i < n) {
+#pragma unroll
+      for (int o = 0; o < NOUT; ++o) a.out[o][out_off + i] = Y[o][s];
+    }
+  }
+}
+
+}  // namespace hentt

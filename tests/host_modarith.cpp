@@ -1,0 +1,68 @@
+// CPU property test of the device modular arithmetic (modarith.hpp built for
+// the host).  Checks Algorithm 1's contract (inputs and outputs in [0, 4q),
+// X' = X + W Y, Y' = X - W Y mod q), the inverse butterfly's [0, 2q) contract,
+// and the Barrett/Shoup/mad_mod products against exact 128-bit arithmetic.
+#include <stdint.h>
+#include <stdio.h>
+#include <random>
+#define HENTT_HOST_TEST 1
+#include "../paper_2109_14704_amd/csrc/modarith.hpp"
+
+typedef unsigned __int128 u128;
+using namespace hentt;
+
+static int fails = 0;
+#define EXPECT(c, ...)                       \
+  do {                                       \
+    if (!(c)) {                              \
+      if (fails++ < 10) printf(__VA_ARGS__); \
+    }                                        \
+  } while (0)
+
+static uint64_t mm(uint64_t a, uint64_t b, uint64_t q) { return (uint64_t)((u128)a * b % q); }
+
+int main(int argc, char **argv) {
+  long iters = argc > 1 ? atol(argv[1]) : 200000;
+  std::mt19937_64 g(2109);
+  for (long it = 0; it < iters; ++it) {
+    int k = 8 + (int)(g() % 53);                    // bit length 8..60
+    uint64_t q = ((g() >> (64 - k)) | (1ull << (k - 1))) | 1;
+    if (it % 7 == 0) q = (k == 60) ? ((1ull << 60) - 1) : ((1ull << k) - 1);
+    uint64_t q2 = 2 * q, q4 = 4 * q;
+    uint64_t a = g(), b = g();
+    u128 full = (u128)a * b;
+    EXPECT(mulhi64(a, b) == (uint64_t)(full >> 64), "mulhi64 %llx %llx\n", (unsigned long long)a, (unsigned long long)b);
+    uint64_t h, l;
+    mul128(a, b, h, l);
+    EXPECT(h == (uint64_t)(full >> 64) && l == (uint64_t)full, "mul128\n");
+    // Shoup product for any Y < 2^64
+    uint64_t W = (it % 11 == 0) ? (q - 1) : (it % 13 == 0 ? 0 : g() % q);
+    uint64_t Ws = (uint64_t)(((u128)W << 64) / q);
+    uint64_t Y = (it % 5 == 0) ? ~0ull : g();
+    uint64_t T = shoup(W, Ws, Y, q);
+    EXPECT(T < q2 && T % q == mm(W, Y % q, q), "shoup q=%llx\n", (unsigned long long)q);
+    // forward butterfly, Algorithm 1
+    uint64_t X = (it % 3 == 0) ? q4 - 1 : g() % q4, Yb = (it % 4 == 0) ? q4 - 1 : g() % q4;
+    uint64_t x1 = X, y1 = Yb;
+    ct_bfly(x1, y1, W, Ws, q, q2);
+    uint64_t wy = mm(W, Yb % q, q);
+    EXPECT(x1 < q4 && y1 < q4, "ct range\n");
+    EXPECT(x1 % q == (X % q + wy) % q && y1 % q == (X % q + q - wy) % q, "ct value\n");
+    // inverse butterfly
+    uint64_t Xi = g() % q2, Yi = (it % 6 == 0) ? q2 - 1 : g() % q2;
+    uint64_t x2 = Xi, y2 = Yi;
+    gs_bfly(x2, y2, W, Ws, q, q2);
+    EXPECT(x2 < q2 && y2 < q2, "gs range\n");
+    EXPECT(x2 % q == (Xi + Yi) % q && y2 % q == mm(W, (Xi % q + q - Yi % q) % q, q), "gs value\n");
+    // Barrett products on canonical inputs
+    uint32_t kk = 64 - __builtin_clzll(q);
+    uint64_t mu = (uint64_t)(((u128)1 << (2 * kk)) / q);
+    uint64_t u = (it % 9 == 0) ? q - 1 : g() % q, v = (it % 10 == 0) ? q - 1 : g() % q;
+    uint64_t s = (it % 9 == 0) ? q - 1 : g() % q, t = (it % 10 == 0) ? q - 1 : g() % q;
+    EXPECT(mulmod(u, v, q, mu, kk) == mm(u, v, q), "mulmod q=%llx\n", (unsigned long long)q);
+    uint64_t want = (uint64_t)(((u128)u * v + (u128)s * t) % q);
+    EXPECT(madmod(u, v, s, t, q, mu, kk) == want, "madmod q=%llx\n", (unsigned long long)q);
+  }
+  printf(fails ? "FAIL %d\n" : "OK\n", fails);
+  return fails ? 1 : 0;
+}

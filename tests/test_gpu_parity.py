@@ -1,0 +1,238 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+All integer work, so the bar is bit-exactness everywhere.  Small cases are
+compared element by element; full workload sizes are compared on sampled
+outputs the oracle evaluates one by one (O(N) each) plus properties that
+hold at any size (round trip).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+CHAIN = workloads.moduli("uneven")          # q = 1 mod 2^18: valid for every N <= 2^17
+
+
+def dev(a, device):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).to(device)
+
+
+def host(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+def rand_limbs(rng, shape, mods):
+    out = np.empty(shape, dtype=np.uint64)
+    for l, q in enumerate(mods):
+        out[..., l, :] = rng.integers(0, q, size=shape[:-2] + (shape[-1],), dtype=np.uint64)
+    return out
+
+
+@pytest.mark.parametrize("log_n", list(range(6, 18)))
+def test_fwd_inv_every_size(gpu, log_n):
+    import paper_2109_14704_amd as H
+    print("case fwd/inv log_n=%d" % log_n, flush=True)
+    rng = np.random.default_rng(log_n)
+    limbs = 3 if log_n <= 14 else 2
+    batch = 3 if log_n <= 15 else 2
+    mods = CHAIN[:limbs]
+    x = rand_limbs(rng, (batch, limbs, 1 << log_n), mods)
+    # edge values: zeros, q-1 everywhere, a monomial
+    x[0, 0, :] = 0
+    x[-1, -1, :] = mods[-1] - 1
+    t = H.Tables(log_n, mods)
+    d = dev(x, gpu)
+    H.ntt_fwd(t, d)
+    want = oracle.batch_ntt(x, mods, +1)
+    assert np.array_equal(host(d), want)
+    H.ntt_inv(t, d)
+    assert np.array_equal(host(d), x)
+    # inverse alone on arbitrary canonical NTT-domain input
+    d2 = dev(want, gpu)
+    H.ntt_inv(t, d2)
+    assert np.array_equal(host(d2), x)
+
+
+@pytest.mark.parametrize("log_n", [6, 12, 14, 15, 17])
+def test_dyadic_and_polymul(gpu, log_n):
+    import paper_2109_14704_amd as H
+    print("case dyadic/polymul log_n=%d" % log_n, flush=True)
+    rng = np.random.default_rng(100 + log_n)
+    mods = CHAIN[:2]
+    a = rand_limbs(rng, (2, 2, 1 << log_n), mods)
+    b = rand_limbs(rng, (2, 2, 1 << log_n), mods)
+    t = H.Tables(log_n, mods)
+    out = H.dyadic_mul(t, dev(a, gpu), dev(b, gpu))
+    assert np.array_equal(host(out), oracle.batch_dyadic(a, b, mods))
+    p = H.polymul(t, dev(a, gpu), dev(b, gpu))
+    assert np.array_equal(host(p), oracle.batch_polymul(a, b, mods))
+
+
+@pytest.mark.parametrize("log_n", [6, 13, 16])
+@pytest.mark.parametrize("in_ntt,out_ntt", [(False, False), (True, False), (False, True), (True, True)])
+def test_ct_tensor_flags(gpu, log_n, in_ntt, out_ntt):
+    import paper_2109_14704_amd as H
+    print("case ct_tensor log_n=%d in_ntt=%s out_ntt=%s" % (log_n, in_ntt, out_ntt), flush=True)
+    rng = np.random.default_rng(200 + log_n)
+    mods = CHAIN[:3]
+    c = rand_limbs(rng, (2, 2, 3, 1 << log_n), mods)
+    d = rand_limbs(rng, (2, 2, 3, 1 << log_n), mods)
+    C = oracle.batch_ntt(c, mods, +1)
+    D = oracle.batch_ntt(d, mods, +1)
+    T = oracle.batch_tensor(C, D, mods)
+    want = T if out_ntt else oracle.batch_ntt(T, mods, -1)
+    t = H.Tables(log_n, mods)
+    cin, din = (C, D) if in_ntt else (c, d)
+    cd, dd = dev(cin, gpu), dev(din, gpu)
+    out = H.ct_tensor(t, cd, dd, in_ntt=in_ntt, out_ntt=out_ntt)
+    assert np.array_equal(host(out), want)
+    assert np.array_equal(host(cd), cin) and np.array_equal(host(dd), din)   # inputs untouched
+
+
+def test_plain4096_workload(gpu):
+    """Workload 1 at full size: 8 polys fwd + inv, one polymul vs schoolbook."""
+    import paper_2109_14704_amd as H
+    w = workloads.plain4096()
+    q = w["moduli"]
+    t = H.Tables(12, q)
+    x = dev(w["x"], gpu)
+    H.ntt_fwd(t, x)
+    assert np.array_equal(host(x), oracle.batch_ntt(w["x"], q, +1))
+    H.ntt_inv(t, x)
+    assert np.array_equal(host(x), w["x"])
+    p = H.polymul(t, dev(w["a"], gpu), dev(w["b"], gpu))
+    assert np.array_equal(host(p)[0, 0], oracle.negacyclic_schoolbook(w["a"][0, 0], w["b"][0, 0], q[0]))
+
+
+def _sample_points(rng, n, k):
+    return sorted(set([0, n - 1] + [int(v) for v in rng.integers(0, n, size=k)]))
+
+
+def test_ckks_level_workload_sampled(gpu):
+    """Workload 2 at full size [128][16][2^15]: fwd, dyadic, inv; sampled outputs."""
+    import paper_2109_14704_amd as H
+    w = workloads.ckks_level()
+    mods, ln = w["moduli"], w["log_n"]
+    n = 1 << ln
+    t = H.Tables(ln, mods)
+    A, B = dev(w["a"], gpu), dev(w["b"], gpu)
+    H.ntt_fwd(t, A)
+    H.ntt_fwd(t, B)
+    fa = host(A)
+    rng = np.random.default_rng(5)
+    for (bi, l) in [(0, 0), (127, 15), (64, 7), (3, 11)]:
+        ps = oracle.psi(mods[l], ln)
+        for k in _sample_points(rng, n, 6):
+            assert int(fa[bi, l, k]) == oracle.ntt_fwd_point(w["a"][bi, l], mods[l], ln, k, ps)
+    H.dyadic_mul(t, A, B, out=A)
+    H.ntt_inv(t, A)
+    prod = host(A)
+    for (bi, l) in [(0, 0), (127, 15), (31, 4)]:
+        for k in _sample_points(rng, n, 4):
+            assert int(prod[bi, l, k]) == oracle.negacyclic_point(w["a"][bi, l], w["b"][bi, l], mods[l], k)
+    # fused polymul gives the same words
+    P = H.polymul(t, dev(w["a"], gpu), dev(w["b"], gpu))
+    assert np.array_equal(host(P), prod)
+
+
+def test_ct_tensor_workload_sampled(gpu):
+    """Workload 3 at full size: [32][2][24][2^16] pairs -> [32][3][24][2^16]; sampled outputs."""
+    import paper_2109_14704_amd as H
+    w = workloads.ct_tensor()
+    mods, ln = w["moduli"], w["log_n"]
+    n = 1 << ln
+    t = H.Tables(ln, mods)
+    out = host(H.ct_tensor(t, dev(w["c"], gpu), dev(w["d"], gpu)))
+    rng = np.random.default_rng(6)
+    c, d = w["c"], w["d"]
+    for (bi, l) in [(0, 0), (31, 23), (17, 9)]:
+        q = mods[l]
+        for k in _sample_points(rng, n, 3):
+            c0d0 = oracle.negacyclic_point(c[bi, 0, l], d[bi, 0, l], q, k)
+            c0d1 = oracle.negacyclic_point(c[bi, 0, l], d[bi, 1, l], q, k)
+            c1d0 = oracle.negacyclic_point(c[bi, 1, l], d[bi, 0, l], q, k)
+            c1d1 = oracle.negacyclic_point(c[bi, 1, l], d[bi, 1, l], q, k)
+            assert int(out[bi, 0, l, k]) == c0d0
+            assert int(out[bi, 1, l, k]) == (c0d1 + c1d0) % q
+            assert int(out[bi, 2, l, k]) == c1d1
+
+
+def test_uneven_batch_matches_oracle(gpu):
+    """Workload 4 shape mix (reduced count): one ntt_batch call vs the oracle per job."""
+    import paper_2109_14704_amd as H
+    mods = workloads.moduli("uneven")
+    jobs = workloads.uneven_jobs(njobs=24)
+    tables = {ln: H.Tables(ln, mods) for ln in range(12, 18)}
+    xs, devs = [], []
+    for j, (ln, L) in enumerate(jobs):
+        x = workloads.uneven_operand(j, ln, L, mods)
+        xs.append(x)
+        devs.append(dev(x, gpu))
+    H.ntt_batch([(d_, tables[ln], L) for d_, (ln, L) in zip(devs, jobs)], +1)
+    for j, (ln, L) in enumerate(jobs):
+        got = host(devs[j])
+        if (1 << ln) * L <= (1 << 17) * 4:
+            assert np.array_equal(got, oracle.batch_ntt(xs[j], mods[:L], +1)), j
+        else:
+            rng = np.random.default_rng(j)
+            for l in [0, L - 1]:
+                for k in _sample_points(rng, 1 << ln, 2):
+                    assert int(got[0, l, k]) == oracle.ntt_fwd_point(xs[j][0, l], mods[l], ln, k)
+    H.ntt_batch([(d_, tables[ln], L) for d_, (ln, L) in zip(devs, jobs)], -1)
+    for j in range(len(jobs)):
+        assert np.array_equal(host(devs[j]), xs[j]), j
+
+
+def test_views_and_levels(gpu):
+    """A view on the first l moduli transforms exactly like tables built for them."""
+    import paper_2109_14704_amd as H
+    mods = workloads.moduli("serving")
+    t = H.Tables(14, mods)
+    v = t.view(5)
+    rng = np.random.default_rng(9)
+    x = rand_limbs(rng, (2, 5, 1 << 14), mods[:5])
+    d = dev(x, gpu)
+    H.ntt_fwd(v, d)
+    assert np.array_equal(host(d), oracle.batch_ntt(x, mods[:5], +1))
+    del t
+    H.ntt_inv(v, d)
+    assert np.array_equal(host(d), x)
+
+
+@pytest.mark.parametrize("log_n,pairs,limbs", [(12, 16, 8), (16, 8, 6)])
+def test_repeat_determinism(gpu, log_n, pairs, limbs):
+    """Identical launches give identical words (every kernel shape, many workgroups)."""
+    import torch
+    import paper_2109_14704_amd as H
+    print("case determinism log_n=%d pairs=%d limbs=%d" % (log_n, pairs, limbs), flush=True)
+    mods = workloads.moduli("ct_tensor")[:limbs]
+    rng = np.random.default_rng(77)
+    c = rand_limbs(rng, (pairs, 2, limbs, 1 << log_n), mods)
+    d = rand_limbs(rng, (pairs, 2, limbs, 1 << log_n), mods)
+    t = H.Tables(log_n, mods)
+    cd, dd = dev(c, gpu), dev(d, gpu)
+    outs = {k: [] for k in ["coeff", "ntt", "poly", "fwd", "dyad"]}
+    for _ in range(3):
+        outs["coeff"].append(H.ct_tensor(t, cd, dd))
+        outs["ntt"].append(H.ct_tensor(t, cd, dd, in_ntt=True, out_ntt=True))
+        outs["poly"].append(H.polymul(t, cd[:, 0], dd[:, 1].contiguous()) if False else
+                            H.polymul(t, cd[:, 0].contiguous(), dd[:, 1].contiguous()))
+        x = cd.clone()
+        outs["fwd"].append(H.ntt_fwd(t, x.view(-1, limbs, 1 << log_n)))
+        outs["dyad"].append(H.dyadic_mul(t, cd, dd))
+    torch.cuda.synchronize()
+    for k, v in outs.items():
+        assert torch.equal(v[0], v[1]) and torch.equal(v[0], v[2]), k
+    # spot-check against the oracle
+    got = host(outs["coeff"][0])
+    q = mods[-1]
+    for k in [0, 5, (1 << log_n) - 1]:
+        want = (oracle.negacyclic_point(c[-1, 0, -1], d[-1, 1, -1], q, k)
+                + oracle.negacyclic_point(c[-1, 1, -1], d[-1, 0, -1], q, k)) % q
+        assert int(got[-1, 1, -1, k]) == want
+    nt = host(outs["ntt"][0])
+    assert np.array_equal(nt, oracle.batch_tensor(c, d, mods))

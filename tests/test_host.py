@@ -1,0 +1,88 @@
+"""CPU-only checks of the library's host side and of its arithmetic.
+
+- the C-ABI library loads and exports every symbol include/hentt.h declares;
+- argument and modulus validation returns the documented status codes
+  (these paths return before any device work);
+- the library's psi agrees with the oracle's for every modulus chain;
+- the device modular arithmetic, built for the host, keeps Algorithm 1's
+  contracts and matches exact 128-bit arithmetic.
+"""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import oracle
+import workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hentt.h")
+
+
+def _lib():
+    import paper_2109_14704_amd as H
+    return H, H.lib()
+
+
+def test_exports_every_declared_symbol():
+    H, L = _lib()
+    names = set(re.findall(r"\b(hentt_[a-z_0-9]+)\s*\(", open(HEADER).read()))
+    assert len(names) >= 14
+    for n in sorted(names):
+        assert hasattr(L, n), n
+
+
+def test_psi_agrees_with_oracle():
+    H, _ = _lib()
+    for name in ["plain4096", "ckks_level", "ct_tensor", "uneven"]:
+        for q in workloads.moduli(name):
+            for ln in range(6, 18):
+                if (q - 1) % (2 << ln) == 0:
+                    assert H.psi(q, ln) == oracle.psi(q, ln), (name, q, ln)
+
+
+def test_status_codes():
+    H, L = _lib()
+    U64 = ctypes.c_uint64
+    out = ctypes.c_void_p()
+    good = workloads.moduli("uneven")[0]
+
+    def create(log_n, mods):
+        arr = (U64 * max(1, len(mods)))(*mods)
+        return L.hentt_tables_create(log_n, len(mods), arr, None, ctypes.byref(out))
+
+    assert create(5, [good]) == -1          # log_n below range
+    assert create(18, [good]) == -1         # log_n above range
+    assert create(12, []) == -1             # zero limbs
+    assert create(12, [good + 2]) == -2     # not 1 mod 2N / not prime
+    assert create(12, [(1 << 60) + 1]) == -2   # 1 mod 2N but >= 2^60
+    composite = 8193 * 16385                    # 1 mod 8192, composite
+    assert (composite - 1) % 8192 == 0 and create(12, [composite]) == -2
+    assert create(12, [97]) == -2           # below 2^7 / not 1 mod 8192
+    assert L.hentt_tables_create(12, 1, None, None, ctypes.byref(out)) == -1
+    assert L.hentt_ntt_fwd(None, None, 1, None) == -1
+    assert L.hentt_ntt_inv(None, None, 1, None) == -1
+    assert L.hentt_dyadic_mul(None, None, None, None, 1, None) == -1
+    assert L.hentt_polymul(None, None, None, None, 1, None) == -1
+    assert L.hentt_ct_tensor(None, None, None, None, 1, 0, None) == -1
+    assert L.hentt_ntt_batch(None, 0, 1, None) == -1
+    assert L.hentt_tables_destroy(None) == -1
+    assert L.hentt_status_str(-2).decode().startswith("bad modulus")
+    with pytest.raises(H.HenttError):
+        H.psi(good + 2, 12)
+
+
+def test_device_arithmetic_on_host(tmp_path):
+    exe = str(tmp_path / "host_modarith")
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-o", exe, os.path.join(ROOT, "tests", "host_modarith.cpp")])
+    r = subprocess.run([exe, "300000"], stdout=subprocess.PIPE, text=True, timeout=300)
+    assert r.returncode == 0 and r.stdout.strip().endswith("OK"), r.stdout
+
+
+def test_roofline_accounting_reproduces_table_one():
+    from paper_2109_14704_amd import roofline
+    # section IV-B: naive radix-2 density 1.5, staged radix-8 SLM density 8.9 at N = 32K
+    assert roofline.paper_density("naive", 1 << 15) == pytest.approx(1.5)
+    assert roofline.paper_density("radix8_slm", 1 << 15) == pytest.approx(8.906, abs=1e-3)
