@@ -33,6 +33,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-per-poly", action="store_true", help="skip the per-polynomial comparator")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU work for the oracle sample")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -129,9 +131,11 @@ def cpu_plain(w, k):
 
 def cpu_baseline(s, target_s):
     import oracle
-    dt1, c1 = s["cpu"](1)                       # calibration: one batch entry
-    k = max(1, min(int(target_s / max(dt1, 1e-3)), 64))
-    dt, coeffs = s["cpu"](k) if k > 1 else (dt1, c1)
+    k, limit = 1, len(s["w"].get("a", s["w"].get("c", s["w"].get("x"))))
+    dt, coeffs = s["cpu"](k)
+    while dt < target_s / 2 and k < limit:      # grow the sample to about the target time
+        k = min(limit, max(k + 1, int(k * target_s / max(dt, 1e-3))))
+        dt, coeffs = s["cpu"](k)
     return {"value": coeffs / dt / 1e9, "unit": "Gcoeff/s", "cores": oracle.max_threads(), "kind": "oracle",
             "sample": "%d batch entr%s of the same workload (radix-2 oracle, OpenMP over (batch, limb)), %.1f s"
                       % (k, "y" if k == 1 else "ies", dt)}
@@ -255,6 +259,13 @@ def main():
         pms = a.elapsed_time(b) / reps
         result["per_poly"] = {"ms_per_step": round(pms, 4), "value": round(s["coeffs"] / (pms / 1e3) / 1e9, 3),
                               "unit": "Gcoeff/s", "batched_speedup": round(pms / ms, 3)}
+    if args.calib_copy:
+        src = torch.ones(1 << 27, dtype=torch.int64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if not args.no_cpu:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(s, args.cpu_seconds)

@@ -224,9 +224,14 @@ template <int LOGN> struct Plan {
   static constexpr bool WHOLE = LOGN <= 14;
   static constexpr int EC = LOGN <= 15 ? (LOGN - 12 > 0 ? LOGN - 12 : 1) : (LOGN == 16 ? 4 : 4);
   static constexpr int B = LOGN - EC;
-  // fused products: one kernel up to 2^12, else column pass + blocks
+  // fused products: one kernel up to 2^12, else a column pass of PEC stages
+  // and blocks of 2^12 coefficients
   static constexpr bool PROD_WHOLE = LOGN <= 12;
+  static constexpr int PEC = LOGN > 12 ? LOGN - 12 : 1;
 };
+// Elements per lane (2^E) in the fused product kernels: the tensor keeps four
+// transformed inputs live, so it uses 8 per lane to stay within the VGPRs.
+template <int MODE> struct ProdE { static constexpr int E = MODE == PROD_MUL ? 4 : 3; };
 
 ColArgs col_args(uint64_t *x, uint64_t sb) {
   ColArgs a{};
@@ -289,13 +294,14 @@ void launch_prod(const hentt_tables *t, const ProdArgs &pa, uint32_t batch, bool
     { LaunchTimer lt_(MODE == PROD_MUL ? "k_elem_mul" : "k_elem_tensor", LOGN, st); hipLaunchKernelGGL((k_elem<MODE>), dim3(units * tiles), dim3(256), 0, st, pa, lc, batch, L, (uint32_t)LOGN, tiles); }
     return;
   }
+  constexpr int PE = ProdE<MODE>::E;
   if constexpr (P::PROD_WHOLE) {
-    const dim3 g(units), blk(1 << (LOGN - 4));
-    if (in_coeff && out_coeff) { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, LOGN, 4, MODE, true, true>), g, blk, 0, st, pa, tw, lc, batch, L); }
-    else if (in_coeff) { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, LOGN, 4, MODE, true, false>), g, blk, 0, st, pa, tw, lc, batch, L); }
-    else { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, LOGN, 4, MODE, false, true>), g, blk, 0, st, pa, tw, lc, batch, L); }
+    const dim3 g(units), blk(1 << (LOGN - PE));
+    if (in_coeff && out_coeff) { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, LOGN, PE, MODE, true, true>), g, blk, 0, st, pa, tw, lc, batch, L); }
+    else if (in_coeff) { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, LOGN, PE, MODE, true, false>), g, blk, 0, st, pa, tw, lc, batch, L); }
+    else { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, LOGN, PE, MODE, false, true>), g, blk, 0, st, pa, tw, lc, batch, L); }
   } else {
-    constexpr int EC = P::EC, B = P::B;
+    constexpr int EC = P::PEC, B = LOGN - P::PEC;
     const uint64_t NL = (uint64_t)L << LOGN;
     ProdArgs pb = pa;
     if (in_coeff) {
@@ -312,10 +318,10 @@ void launch_prod(const hentt_tables *t, const ProdArgs &pa, uint32_t batch, bool
       { LaunchTimer lt_("k_cols_fwd", LOGN, st); hipLaunchKernelGGL((k_cols<LOGN, EC, false>), dim3(NIN * units * ((1u << (LOGN - EC)) / 256)), dim3(256), 0, st,
                          ca, tw, lc, batch, L); }
     }
-    const dim3 g(units << (LOGN - B)), blk(1 << (B - 4));
-    if (in_coeff && out_coeff) { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, B, 4, MODE, true, true>), g, blk, 0, st, pb, tw, lc, batch, L); }
-    else if (in_coeff) { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, B, 4, MODE, true, false>), g, blk, 0, st, pb, tw, lc, batch, L); }
-    else { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, B, 4, MODE, false, true>), g, blk, 0, st, pb, tw, lc, batch, L); }
+    const dim3 g(units << (LOGN - B)), blk(1 << (B - PE));
+    if (in_coeff && out_coeff) { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, B, PE, MODE, true, true>), g, blk, 0, st, pb, tw, lc, batch, L); }
+    else if (in_coeff) { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, B, PE, MODE, true, false>), g, blk, 0, st, pb, tw, lc, batch, L); }
+    else { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, B, PE, MODE, false, true>), g, blk, 0, st, pb, tw, lc, batch, L); }
     if (out_coeff) {
       ColArgs ca{};
       for (int o = 0; o < NOUT; ++o) ca.src[o] = ca.dst[o] = pa.out[o];
@@ -425,8 +431,12 @@ int hentt_tables_create(uint32_t log_n, uint32_t limbs, const uint64_t *moduli_h
     }
     LimbConst &c = lc[l];
     memset(&c, 0, sizeof(c));
-    c.q = q;
-    c.q2 = 2 * q;
+    c.m.q = q;
+    c.m.nq = 0 - q;
+    c.m.q2 = 2 * q;
+    c.m.nq2 = 0 - 2 * q;
+    c.m.q4 = 4 * q;
+    c.m.nq4 = 0 - 4 * q;
     c.ninv = h_pow(N % q, q - 2, q);
     c.ninv_s = shoup_quot(c.ninv, q);
     c.ninvw = h_mul(c.ninv, iv[1].w, q);

@@ -40,35 +40,62 @@ __device__ __forceinline__ void mul128(uint64_t a, uint64_t b, uint64_t& hi, uin
   hi = mad32(a1, b1, hi32(m1)) + hi32(m2);
 }
 
-// Shoup product: W*Y mod q up to one multiple of q, W' = floor(W 2^64 / q).
-// Result in [0, 2q) for any Y < 2^64 (Harvey 2014, the butterfly of
-// Algorithm 1 in section III-B).
-__device__ __forceinline__ uint64_t shoup(uint64_t W, uint64_t Ws, uint64_t Y, uint64_t q) {
-  uint64_t Q = mulhi64(Ws, Y);
-  return W * Y - Q * q;
+// Quotient estimate for Shoup's product: floor(W' Y / 2^64) minus 0, 1 or 2.
+// Only the three high partial products enter (a1 b1 and the high halves of
+// the cross products); the low product a0 b0 and the low halves of the
+// cross products, which together carry less than 3 into bit 64, are dropped.
+// Three multiplies instead of four, and no carry chain.
+__device__ __forceinline__ uint64_t shoup_q(uint64_t Ws, uint64_t Y) {
+  const uint32_t a0 = lo32(Ws), a1 = hi32(Ws), b0 = lo32(Y), b1 = hi32(Y);
+  const uint64_t s = (uint64_t)__umulhi(a1, b0) + __umulhi(a0, b1);
+  return mad32(a1, b1, s);
 }
 
+// Shoup product (Harvey 2014, the butterfly of Algorithm 1 in section III-B):
+// W Y mod q up to a multiple of q, W' = floor(W 2^64 / q), nq = -q mod 2^64.
+// With the estimate above the result lies in [0, 4q) for any Y < 2^64
+// (exact quotient: [0, 2q); each missing unit of the quotient adds q).
+__device__ __forceinline__ uint64_t shoup(uint64_t W, uint64_t Ws, uint64_t Y, uint64_t nq) {
+  return W * Y + shoup_q(Ws, Y) * nq;  // = W Y - Q q  (mod 2^64)
+}
+
+// x >= m ? x - m : x, given nm = -m mod 2^64 (one 64-bit add, one compare).
+__device__ __forceinline__ uint64_t csubn(uint64_t x, uint64_t nm) {
+  const uint64_t d = x + nm;
+  return d < x ? d : x;
+}
 __device__ __forceinline__ uint64_t csub(uint64_t x, uint64_t m) { return x >= m ? x - m : x; }
 
-// Forward (Cooley-Tukey) lazy butterfly, Algorithm 1: X, Y in [0, 4q) on
-// entry and exit; X' = X + W Y, Y' = X - W Y (mod q).
-__device__ __forceinline__ void ct_bfly(uint64_t& X, uint64_t& Y, uint64_t W, uint64_t Ws, uint64_t q,
-                                        uint64_t q2) {
-  uint64_t x = csub(X, q2);
-  uint64_t T = shoup(W, Ws, Y, q);
+// Moduli constants used by the butterflies.
+struct ModQ {
+  uint64_t q, nq, q2, nq2, q4, nq4;  // q, 2q, 4q and their negations mod 2^64
+};
+
+// Forward (Cooley-Tukey) lazy butterfly, Algorithm 1 with a wider lazy range:
+// X, Y in [0, 8q) on entry and exit (q < 2^60); X' = X + W Y, Y' = X - W Y
+// (mod q).  X is brought below 4q, T = W Y mod q lies in [0, 4q), so X + T and
+// X - T + 4q stay in [0, 8q).
+__device__ __forceinline__ void ct_bfly(uint64_t &X, uint64_t &Y, uint64_t W, uint64_t Ws, const ModQ &m) {
+  const uint64_t x = csubn(X, m.nq4);
+  const uint64_t T = shoup(W, Ws, Y, m.nq);
   X = x + T;
-  Y = x - T + q2;
+  Y = (x + m.q4) - T;
 }
 
-// Inverse (Gentleman-Sande) lazy butterfly after Harvey: X, Y in [0, 2q) on
+// Inverse (Gentleman-Sande) lazy butterfly after Harvey: X, Y in [0, 4q) on
 // entry and exit; X' = X + Y, Y' = W (X - Y) (mod q).
-__device__ __forceinline__ void gs_bfly(uint64_t& X, uint64_t& Y, uint64_t W, uint64_t Ws, uint64_t q,
-                                        uint64_t q2) {
-  uint64_t s = X + Y;
-  uint64_t d = X - Y + q2;
-  X = csub(s, q2);
-  Y = shoup(W, Ws, d, q);
+__device__ __forceinline__ void gs_bfly(uint64_t &X, uint64_t &Y, uint64_t W, uint64_t Ws, const ModQ &m) {
+  const uint64_t s = X + Y;
+  const uint64_t d = (X + m.q4) - Y;
+  X = csubn(s, m.nq4);
+  Y = shoup(W, Ws, d, m.nq);
 }
+
+// Canonical reductions: from [0, 8q) and from [0, 4q) to [0, q).
+__device__ __forceinline__ uint64_t reduce_8q(uint64_t x, const ModQ &m) {
+  return csubn(csubn(csubn(x, m.nq4), m.nq2), m.nq);
+}
+__device__ __forceinline__ uint64_t reduce_4q(uint64_t x, const ModQ &m) { return csubn(csubn(x, m.nq2), m.nq); }
 
 // Barrett reduction of a 128-bit z < 2^(2k+1) modulo q, 2^(k-1) <= q < 2^k
 // (k <= 60), with mu = floor(2^(2k) / q): quotient estimate

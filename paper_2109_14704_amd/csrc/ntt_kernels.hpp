@@ -15,15 +15,17 @@
 // the staged global -> local -> register design of section III-B, with the
 // radix-2^R register blocking of its high-radix subsection.
 #pragma once
+#include <type_traits>
+
 #include "modarith.hpp"
 
 namespace hentt {
 
 struct LimbConst {
-  uint64_t q, q2;         // q, 2q
-  uint64_t ninv, ninv_s;  // N^-1 mod q and its Shoup quotient
+  ModQ m;                   // q, 2q, 4q and their negations mod 2^64
+  uint64_t ninv, ninv_s;    // N^-1 mod q and its Shoup quotient
   uint64_t ninvw, ninvw_s;  // N^-1 * psi^-brv(1) mod q and its Shoup quotient
-  uint64_t mu;            // floor(2^(2k) / q), k = bit length of q (Barrett)
+  uint64_t mu;              // floor(2^(2k) / q), k = bit length of q (Barrett)
   uint32_t k, pad;
 };
 
@@ -66,7 +68,7 @@ struct RoundMap {
 // pairs j with j + N/2^(s+1) and uses psi_rev[2^s + (j >> (LOGN - s))].
 template <int LOGN, int B, int E, int LO, int R>
 __device__ __forceinline__ void fwd_round(uint64_t (&x)[1 << E], uint32_t blockStart, uint32_t lanePart,
-                                          const Tw* __restrict__ tw, uint64_t q, uint64_t q2) {
+                                          const Tw* __restrict__ tw, const ModQ &m) {
   using M = RoundMap<B, E, LO, R>;
 #pragma unroll
   for (int g = 0; g < (1 << (E - R)); ++g) {
@@ -80,7 +82,7 @@ __device__ __forceinline__ void fwd_round(uint64_t (&x)[1 << E], uint32_t blockS
       for (int k = 0; k < (1 << R); ++k) {
         if (k & h) continue;
         const Tw w = tw[base + (k >> (R - u))];
-        ct_bfly(x[(g << R) + k], x[(g << R) + k + h], w.w, w.ws, q, q2);
+        ct_bfly(x[(g << R) + k], x[(g << R) + k + h], w.w, w.ws, m);
       }
     }
   }
@@ -107,9 +109,9 @@ __device__ __forceinline__ void inv_round(uint64_t (&x)[1 << E], uint32_t blockS
           if (k & d) continue;
           uint64_t& X = x[(g << R) + k];
           uint64_t& Y = x[(g << R) + k + d];
-          uint64_t s = X + Y, df = X - Y + c.q2;
-          X = shoup(c.ninv, c.ninv_s, s, c.q);
-          Y = shoup(c.ninvw, c.ninvw_s, df, c.q);
+          const uint64_t s = X + Y, df = (X + c.m.q4) - Y;
+          X = shoup(c.ninv, c.ninv_s, s, c.m.nq);
+          Y = shoup(c.ninvw, c.ninvw_s, df, c.m.nq);
         }
       } else {
         const uint32_t base = (uint32_t)((1u << LOGN) >> (v + 1)) + (J0 >> (v + 1));
@@ -117,7 +119,7 @@ __device__ __forceinline__ void inv_round(uint64_t (&x)[1 << E], uint32_t blockS
         for (int k = 0; k < (1 << R); ++k) {
           if (k & d) continue;
           const Tw w = itw[base + (k >> (u + 1))];
-          gs_bfly(x[(g << R) + k], x[(g << R) + k + d], w.w, w.ws, c.q, c.q2);
+          gs_bfly(x[(g << R) + k], x[(g << R) + k + d], w.w, w.ws, c.m);
         }
       }
     }
@@ -150,14 +152,14 @@ __device__ __forceinline__ void store_lds(const uint64_t (&x)[1 << E], uint64_t*
   for (int s = 0; s < (1 << E); ++s) lds[lds_pad(lp + M::slot_part(s))] = x[s];
 }
 
-// Canonical reductions.
-template <int E> __device__ __forceinline__ void reduce4(uint64_t (&x)[1 << E], uint64_t q, uint64_t q2) {
+// Canonical reductions of forward outputs ([0, 8q)) and inverse outputs ([0, 4q)).
+template <int E> __device__ __forceinline__ void reduce_fwd(uint64_t (&x)[1 << E], const ModQ &m) {
 #pragma unroll
-  for (int s = 0; s < (1 << E); ++s) x[s] = csub(csub(x[s], q2), q);
+  for (int s = 0; s < (1 << E); ++s) x[s] = reduce_8q(x[s], m);
 }
-template <int E> __device__ __forceinline__ void reduce2(uint64_t (&x)[1 << E], uint64_t q) {
+template <int E> __device__ __forceinline__ void reduce_inv(uint64_t (&x)[1 << E], const ModQ &m) {
 #pragma unroll
-  for (int s = 0; s < (1 << E); ++s) x[s] = csub(x[s], q);
+  for (int s = 0; s < (1 << E); ++s) x[s] = reduce_4q(x[s], m);
 }
 
 // --------------------------------------------------- block transforms ----
@@ -167,11 +169,10 @@ template <int E> __device__ __forceinline__ void reduce2(uint64_t (&x)[1 << E], 
 // i.e. 2^E consecutive elements, values in [0, 4q).
 template <int LOGN, int B, int E, int LO, int R>
 __device__ __forceinline__ void fwd_block_rounds(uint64_t (&x)[1 << E], uint64_t* lds, uint32_t tid,
-                                                 uint32_t blockStart, const Tw* __restrict__ tw, uint64_t q,
-                                                 uint64_t q2) {
+                                                 uint32_t blockStart, const Tw* __restrict__ tw, const ModQ &m) {
   using M = RoundMap<B, E, LO, R>;
   const uint32_t lp = M::lane_part(tid);
-  fwd_round<LOGN, B, E, LO, R>(x, blockStart, lp, tw, q, q2);
+  fwd_round<LOGN, B, E, LO, R>(x, blockStart, lp, tw, m);
   if constexpr (LO > 0) {
     constexpr int R2 = E;
     constexpr int LO2 = LO - R2;
@@ -180,7 +181,7 @@ __device__ __forceinline__ void fwd_block_rounds(uint64_t (&x)[1 << E], uint64_t
     __syncthreads();
     using M2 = RoundMap<B, E, LO2, R2>;
     load_lds<B, E, LO2, R2>(x, lds, M2::lane_part(tid));
-    fwd_block_rounds<LOGN, B, E, LO2, R2>(x, lds, tid, blockStart, tw, q, q2);
+    fwd_block_rounds<LOGN, B, E, LO2, R2>(x, lds, tid, blockStart, tw, m);
   }
 }
 
@@ -238,15 +239,15 @@ __global__ __launch_bounds__(1 << (LOGN - E)) void k_fwd_whole(uint64_t* __restr
                                                                 uint32_t limbs) {
   __shared__ uint64_t lds[LdsSize<LOGN>::value];
   const Unit un = unit_of(blockIdx.x, 1, batch, limbs);
-  const uint64_t q = lc[un.limb].q, q2 = lc[un.limb].q2;
+  const ModQ m = lc[un.limb].m;
   const Tw* t = tw + (size_t)un.limb * 2 * (1u << LOGN);
   uint64_t* p = x + (size_t)un.poly * (1u << LOGN);
   const uint32_t tid = threadIdx.x;
   using F = FwdFirst<LOGN, E>;
   uint64_t v[1 << E];
   load_global<LOGN, E, F::LO, F::R>(v, p, RoundMap<LOGN, E, F::LO, F::R>::lane_part(tid));
-  fwd_block_rounds<LOGN, LOGN, E, F::LO, F::R>(v, lds, tid, 0, t, q, q2);
-  reduce4<E>(v, q, q2);
+  fwd_block_rounds<LOGN, LOGN, E, F::LO, F::R>(v, lds, tid, 0, t, m);
+  reduce_fwd<E>(v, m);
   store_global<LOGN, E, 0, E>(v, p, RoundMap<LOGN, E, 0, E>::lane_part(tid));
 }
 
@@ -264,7 +265,7 @@ __global__ __launch_bounds__(1 << (LOGN - E)) void k_inv_whole(uint64_t* __restr
   uint64_t v[1 << E];
   load_global<LOGN, E, 0, E>(v, p, RoundMap<LOGN, E, 0, E>::lane_part(tid));
   inv_block_rounds<LOGN, LOGN, E, 0, (LOGN < E ? LOGN : E)>(v, lds, tid, 0, it, c);
-  reduce2<E>(v, c.q);
+  reduce_inv<E>(v, c.m);
   store_global<LOGN, E, L::LO, L::R>(v, p, RoundMap<LOGN, E, L::LO, L::R>::lane_part(tid));
 }
 
@@ -298,11 +299,11 @@ __global__ __launch_bounds__(256) void k_cols(ColArgs a, const Tw *__restrict__ 
   load_global<LOGN, E, LO, E>(v, src, col);
   if constexpr (!INV) {
     const Tw *t = tw + (size_t)limb * 2 * (1u << LOGN);
-    fwd_round<LOGN, LOGN, E, LO, E>(v, 0, col, t, c.q, c.q2);
+    fwd_round<LOGN, LOGN, E, LO, E>(v, 0, col, t, c.m);
   } else {
     const Tw *it = tw + ((size_t)limb * 2 + 1) * (1u << LOGN);
     inv_round<LOGN, LOGN, E, LO, E>(v, 0, col, it, c);
-    reduce2<E>(v, c.q);
+    reduce_inv<E>(v, c.m);
   }
   store_global<LOGN, E, LO, E>(v, dst, col);
 }
@@ -316,7 +317,7 @@ __global__ __launch_bounds__(1 << (B - E)) void k_fwd_blocks(uint64_t *__restric
   __shared__ uint64_t lds[LdsSize<B>::value];
   constexpr uint32_t tiles = 1u << (LOGN - B);
   const Unit un = unit_of(blockIdx.x, tiles, batch, limbs);
-  const uint64_t q = lc[un.limb].q, q2 = lc[un.limb].q2;
+  const ModQ m = lc[un.limb].m;
   const Tw *t = tw + (size_t)un.limb * 2 * (1u << LOGN);
   const uint32_t blockStart = un.tile << B;
   uint64_t *p = x + (size_t)un.poly * (1u << LOGN) + blockStart;
@@ -324,8 +325,8 @@ __global__ __launch_bounds__(1 << (B - E)) void k_fwd_blocks(uint64_t *__restric
   using F = FwdFirst<B, E>;
   uint64_t v[1 << E];
   load_global<B, E, F::LO, F::R>(v, p, RoundMap<B, E, F::LO, F::R>::lane_part(tid));
-  fwd_block_rounds<LOGN, B, E, F::LO, F::R>(v, lds, tid, blockStart, t, q, q2);
-  reduce4<E>(v, q, q2);
+  fwd_block_rounds<LOGN, B, E, F::LO, F::R>(v, lds, tid, blockStart, t, m);
+  reduce_fwd<E>(v, m);
   store_global<B, E, 0, E>(v, p, RoundMap<B, E, 0, E>::lane_part(tid));
 }
 
@@ -350,6 +351,16 @@ __global__ __launch_bounds__(1 << (B - E)) void k_inv_blocks(uint64_t *__restric
 }
 
 // ------------------------------------------------------ fused products ----
+// Compile-time loop: f(std::integral_constant<int, I>) for I in [I0, I1), so
+// that array indices stay constants (no stack arrays) even for loop bodies too
+// large for the unroller.
+template <int I0, int I1, typename F> __device__ __forceinline__ void static_for(F &&f) {
+  if constexpr (I0 < I1) {
+    f(std::integral_constant<int, I0>{});
+    static_for<I0 + 1, I1>(f);
+  }
+}
+
 // Returns p unchanged but hides that from the optimiser (adds an opaque,
 // wave-uniform zero), so loads through it are not merged with earlier ones.
 template <typename T> __device__ __forceinline__ const T *opaque(const T *p) {
@@ -378,11 +389,11 @@ __device__ __forceinline__ void products(uint64_t (&X)[ProdShape<MODE>::NIN][1 <
 #pragma unroll
   for (int s = 0; s < (1 << E); ++s) {
     if constexpr (MODE == PROD_MUL) {
-      Y[0][s] = mulmod(X[0][s], X[1][s], c.q, c.mu, c.k);
+      Y[0][s] = mulmod(X[0][s], X[1][s], c.m.q, c.mu, c.k);
     } else {
-      Y[0][s] = mulmod(X[0][s], X[2][s], c.q, c.mu, c.k);
-      Y[1][s] = madmod(X[0][s], X[3][s], X[1][s], X[2][s], c.q, c.mu, c.k);
-      Y[2][s] = mulmod(X[1][s], X[3][s], c.q, c.mu, c.k);
+      Y[0][s] = mulmod(X[0][s], X[2][s], c.m.q, c.mu, c.k);
+      Y[1][s] = madmod(X[0][s], X[3][s], X[1][s], X[2][s], c.m.q, c.mu, c.k);
+      Y[2][s] = mulmod(X[1][s], X[3][s], c.m.q, c.mu, c.k);
     }
   }
 }
@@ -416,32 +427,54 @@ __global__ __launch_bounds__(1 << (B - E)) void k_prod(ProdArgs a, const Tw *__r
   using F = FwdFirst<B, E>;
   using L = InvLast<B, E>;
   using M0 = RoundMap<B, E, 0, E>;
+  // The transform code appears once for all inputs and once for all outputs
+  // (rolled loops): unrolled per polynomial it would outgrow the instruction
+  // cache.  Results move between the loop's working registers and the
+  // per-polynomial arrays through compile-time-indexed copies.
   uint64_t X[NIN][1 << E];
-#pragma unroll
+#pragma unroll 1
   for (int p = 0; p < NIN; ++p) {
+    uint64_t v[1 << E];
     if constexpr (DO_FWD) {
       if (p > 0) __syncthreads();  // the previous input's last LDS reads are done
       // an opaque copy of the table pointer per input: the twiddles are re-read
-      // from cache for each input instead of being kept live in VGPRs
+      // from cache instead of being hoisted out of the loop into VGPRs
       const Tw *tp = opaque(t);
-      load_global<B, E, F::LO, F::R>(X[p], a.in[p] + in_off, RoundMap<B, E, F::LO, F::R>::lane_part(tid));
-      fwd_block_rounds<LOGN, B, E, F::LO, F::R>(X[p], lds, tid, blockStart, tp, c.q, c.q2);
-      reduce4<E>(X[p], c.q, c.q2);
+      load_global<B, E, F::LO, F::R>(v, a.in[p] + in_off, RoundMap<B, E, F::LO, F::R>::lane_part(tid));
+      fwd_block_rounds<LOGN, B, E, F::LO, F::R>(v, lds, tid, blockStart, tp, c.m);
+      reduce_fwd<E>(v, c.m);
     } else {
-      load_global<B, E, 0, E>(X[p], a.in[p] + in_off, M0::lane_part(tid));
+      load_global<B, E, 0, E>(v, a.in[p] + in_off, M0::lane_part(tid));
     }
+    static_for<0, NIN>([&](auto P) {
+      if (p == decltype(P)::value) {
+        // distinct marker per branch: keeps the branches from being merged
+        // into one dynamically indexed (stack) store
+        if constexpr (MODE == PROD_TENSOR) asm volatile("; sel %0" ::"n"(decltype(P)::value));
+#pragma unroll
+        for (int s2 = 0; s2 < (1 << E); ++s2) X[decltype(P)::value][s2] = v[s2];
+      }
+    });
   }
   uint64_t Y[NOUT][1 << E];
   products<MODE, E>(X, Y, c);
-#pragma unroll
+#pragma unroll 1
   for (int o = 0; o < NOUT; ++o) {
+    uint64_t v[1 << E];
+    static_for<0, NOUT>([&](auto O) {
+      if (o == decltype(O)::value) {
+        if constexpr (MODE == PROD_TENSOR) asm volatile("; sel %0" ::"n"(decltype(O)::value));
+#pragma unroll
+        for (int s2 = 0; s2 < (1 << E); ++s2) v[s2] = Y[decltype(O)::value][s2];
+      }
+    });
     if constexpr (DO_INV) {
       __syncthreads();  // earlier LDS reads of this workgroup are done
-      inv_block_rounds<LOGN, B, E, 0, E>(Y[o], lds, tid, blockStart, opaque(it), c);
-      if constexpr (B == LOGN) reduce2<E>(Y[o], c.q);
-      store_global<B, E, L::LO, L::R>(Y[o], a.out[o] + out_off, RoundMap<B, E, L::LO, L::R>::lane_part(tid));
+      inv_block_rounds<LOGN, B, E, 0, E>(v, lds, tid, blockStart, opaque(it), c);
+      if constexpr (B == LOGN) reduce_inv<E>(v, c.m);
+      store_global<B, E, L::LO, L::R>(v, a.out[o] + out_off, RoundMap<B, E, L::LO, L::R>::lane_part(tid));
     } else {
-      store_global<B, E, 0, E>(Y[o], a.out[o] + out_off, M0::lane_part(tid));
+      store_global<B, E, 0, E>(v, a.out[o] + out_off, M0::lane_part(tid));
     }
   }
 }

@@ -28,32 +28,39 @@ int main(int argc, char **argv) {
     int k = 8 + (int)(g() % 53);                    // bit length 8..60
     uint64_t q = ((g() >> (64 - k)) | (1ull << (k - 1))) | 1;
     if (it % 7 == 0) q = (k == 60) ? ((1ull << 60) - 1) : ((1ull << k) - 1);
-    uint64_t q2 = 2 * q, q4 = 4 * q;
     uint64_t a = g(), b = g();
     u128 full = (u128)a * b;
     EXPECT(mulhi64(a, b) == (uint64_t)(full >> 64), "mulhi64 %llx %llx\n", (unsigned long long)a, (unsigned long long)b);
     uint64_t h, l;
     mul128(a, b, h, l);
     EXPECT(h == (uint64_t)(full >> 64) && l == (uint64_t)full, "mul128\n");
-    // Shoup product for any Y < 2^64
+    ModQ m;
+    m.q = q; m.nq = 0 - q; m.q2 = 2 * q; m.nq2 = 0 - 2 * q; m.q4 = 4 * q; m.nq4 = 0 - 4 * q;
+    // Shoup product with the short quotient estimate: [0, 4q) for any Y < 2^64
     uint64_t W = (it % 11 == 0) ? (q - 1) : (it % 13 == 0 ? 0 : g() % q);
     uint64_t Ws = (uint64_t)(((u128)W << 64) / q);
     uint64_t Y = (it % 5 == 0) ? ~0ull : g();
-    uint64_t T = shoup(W, Ws, Y, q);
-    EXPECT(T < q2 && T % q == mm(W, Y % q, q), "shoup q=%llx\n", (unsigned long long)q);
-    // forward butterfly, Algorithm 1
-    uint64_t X = (it % 3 == 0) ? q4 - 1 : g() % q4, Yb = (it % 4 == 0) ? q4 - 1 : g() % q4;
+    uint64_t T = shoup(W, Ws, Y, m.nq);
+    EXPECT(T < 4 * q && T % q == mm(W, Y % q, q), "shoup q=%llx\n", (unsigned long long)q);
+    uint64_t Qe = shoup_q(Ws, Y), Qx = (uint64_t)(((u128)Ws * Y) >> 64);
+    EXPECT(Qe <= Qx && Qx - Qe <= 2, "quotient estimate\n");
+    // forward butterfly (Algorithm 1, lazy range [0, 8q))
+    uint64_t q8 = 8 * q;
+    uint64_t X = (it % 3 == 0) ? q8 - 1 : g() % q8, Yb = (it % 4 == 0) ? q8 - 1 : g() % q8;
     uint64_t x1 = X, y1 = Yb;
-    ct_bfly(x1, y1, W, Ws, q, q2);
+    ct_bfly(x1, y1, W, Ws, m);
     uint64_t wy = mm(W, Yb % q, q);
-    EXPECT(x1 < q4 && y1 < q4, "ct range\n");
+    EXPECT(x1 < q8 && y1 < q8, "ct range\n");
     EXPECT(x1 % q == (X % q + wy) % q && y1 % q == (X % q + q - wy) % q, "ct value\n");
-    // inverse butterfly
-    uint64_t Xi = g() % q2, Yi = (it % 6 == 0) ? q2 - 1 : g() % q2;
+    // inverse butterfly, lazy range [0, 4q)
+    uint64_t Xi = (it % 7 == 0) ? 4 * q - 1 : g() % (4 * q), Yi = (it % 6 == 0) ? 4 * q - 1 : g() % (4 * q);
     uint64_t x2 = Xi, y2 = Yi;
-    gs_bfly(x2, y2, W, Ws, q, q2);
-    EXPECT(x2 < q2 && y2 < q2, "gs range\n");
+    gs_bfly(x2, y2, W, Ws, m);
+    EXPECT(x2 < 4 * q && y2 < 4 * q, "gs range\n");
     EXPECT(x2 % q == (Xi + Yi) % q && y2 % q == mm(W, (Xi % q + q - Yi % q) % q, q), "gs value\n");
+    // canonical reductions
+    EXPECT(reduce_8q(X, m) == X % q && reduce_4q(Xi, m) == Xi % q, "reduce\n");
+    EXPECT(csubn(X, m.nq4) == (X >= 4 * q ? X - 4 * q : X), "csubn\n");
     // Barrett products on canonical inputs
     uint32_t kk = 64 - __builtin_clzll(q);
     uint64_t mu = (uint64_t)(((u128)1 << (2 * kk)) / q);
