@@ -29,7 +29,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="ckks_level", choices=["ckks_level", "ct_tensor", "plain4096"])
+    ap.add_argument("--workload", default="ckks_level", choices=["ckks_level", "ct_tensor", "plain4096", "uneven"])
+    ap.add_argument("--grid", type=int, default=0, help="persistent workgroups for the uneven batch (0 = tuned/default)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-per-poly", action="store_true", help="skip the per-polynomial comparator")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU work for the oracle sample")
@@ -42,7 +43,14 @@ def to_dev(a, torch):
     return torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).to("cuda:0")
 
 
-def setup(name, torch, H):
+def _tuned_grid(plan, grid_arg, data=None):
+    if grid_arg:
+        return grid_arg
+    from paper_2109_14704_amd import autotune
+    return autotune.persistent_grid(plan, data=data)
+
+
+def setup(name, torch, H, grid_arg=0):
     """Device-resident operands and the step function for a workload."""
     import workloads
     if name == "ckks_level":
@@ -81,6 +89,41 @@ def setup(name, torch, H):
                 "ops": "fwd of c0,c1,d0,d1; tensor (c0d0, c0d1+c1d0, c1d1); inv of 3 outputs"}
         return dict(step=step, per_poly=per_poly_step, coeffs=7 * pairs * L * n, t=t, info=info, w=w,
                     cpu=lambda k: cpu_tensor(w, k), ctmul=pairs)
+    if name == "uneven":
+        mods = workloads.moduli("uneven")
+        jobs = workloads.uneven_jobs()
+        tables = {ln: H.Tables(ln, mods) for ln in sorted(set(ln for ln, _ in jobs))}
+        xs = [to_dev(workloads.uneven_operand(j, ln, L, mods), torch) for j, (ln, L) in enumerate(jobs)]
+        plan_f = H.BatchPlan([(x, tables[ln], L) for x, (ln, L) in zip(xs, jobs)], +1)
+        plan_i = H.BatchPlan([(x, tables[ln], L) for x, (ln, L) in zip(xs, jobs)], -1)
+        grid = _tuned_grid(plan_f, grid_arg, data=xs)
+        plan_f.set_grid(grid)
+        plan_i.set_grid(grid)
+        plan_f.capture()
+        plan_i.capture()
+        coeffs = sum(L << ln for ln, L in jobs)
+
+        def step():
+            plan_f.replay()
+            plan_i.replay()
+
+        views = {(ln, L): tables[ln].view(L) for ln, L in set(jobs)}
+
+        def per_poly_step():              # one launch sequence per polynomial
+            for x, (ln, L) in zip(xs, jobs):
+                H.ntt_fwd(views[(ln, L)], x)
+            for x, (ln, L) in zip(xs, jobs):
+                H.ntt_inv(views[(ln, L)], x)
+
+        info = {"workload": "uneven", "jobs": len(jobs), "N_range": [1 << 12, 1 << 17], "limbs_range": [1, 32],
+                "coefficients": coeffs, "ops": "fwd then inv, each one persistent launch, hipGraph replay",
+                "persistent_grid": grid}
+        def prof_step():                 # same launches outside the graph, so each is event-timed
+            plan_f.run()
+            plan_i.run()
+
+        return dict(step=step, per_poly=per_poly_step, coeffs=2 * coeffs, t=tables, info=info, w={"x": xs},
+                    cpu=lambda k: cpu_uneven(jobs, mods, k), plans=(plan_f, plan_i), prof_step=prof_step)
     w = workloads.plain4096()
     t = H.Tables(12, w["moduli"])
     X = to_dev(w["x"], torch)
@@ -118,6 +161,19 @@ def cpu_tensor(w, k):
     return dt, 7 * c[:, 0].size
 
 
+def cpu_uneven(jobs, mods, k):
+    import oracle
+    import workloads
+    t0 = time.perf_counter()
+    coeffs = 0
+    for j, (ln, L) in enumerate(jobs[:k]):
+        x = workloads.uneven_operand(j, ln, L, mods)
+        X = oracle.batch_ntt(x, mods[:L], +1)
+        oracle.batch_ntt(X, mods[:L], -1)
+        coeffs += 2 * x.size
+    return time.perf_counter() - t0, coeffs
+
+
 def cpu_plain(w, k):
     import oracle
     x = w["x"]
@@ -132,6 +188,8 @@ def cpu_plain(w, k):
 def cpu_baseline(s, target_s):
     import oracle
     k, limit = 1, len(s["w"].get("a", s["w"].get("c", s["w"].get("x"))))
+    if s["info"]["workload"] == "uneven":
+        k = 4
     dt, coeffs = s["cpu"](k)
     while dt < target_s / 2 and k < limit:      # grow the sample to about the target time
         k = min(limit, max(k + 1, int(k * target_s / max(dt, 1e-3))))
@@ -180,12 +238,25 @@ def kernel_work(name, info):
     return None, None
 
 
+def batch_work(info, jobs):
+    """One persistent launch over the uneven batch: each (polynomial, limb) of
+    N = 2^12 is read and written once, larger N twice (two passes); butterflies
+    (N/2) log2 N per (polynomial, limb)."""
+    nbytes = sum(L * (1 << ln) * (16 if ln == 12 else 32) for ln, L in jobs)
+    muls = sum(MUL_BFLY * L * (1 << (ln - 1)) * ln for ln, L in jobs)
+    return float(nbytes), float(muls)
+
+
 def roofline(prof, info, steps):
     from paper_2109_14704_amd import roofline as R
     # dominant kernel by total time
     name, (ms, cnt) = max(prof.items(), key=lambda kv: kv[1][0])
     per_launch_s = ms / 1e3 / cnt
-    nbytes, muls = kernel_work(name, info)
+    if name.startswith("k_batch"):
+        import workloads
+        nbytes, muls = batch_work(info, workloads.uneven_jobs())
+    else:
+        nbytes, muls = kernel_work(name, info)
     if nbytes is None:
         return None, name, per_launch_s
     t_hbm = nbytes / (R.HBM_PEAK_GBS * 1e9)
@@ -212,7 +283,7 @@ def main():
     import paper_2109_14704_amd as H
     H.lib()
     print("bench: setting up workload %s" % args.workload, file=sys.stderr, flush=True)
-    s = setup(args.workload, torch, H)
+    s = setup(args.workload, torch, H, args.grid)
     step = s["step"]
     for _ in range(args.warmup):
         step()
@@ -234,7 +305,7 @@ def main():
     H.prof_enable(True)
     prof_steps = max(3, min(args.steps, 10))
     for _ in range(prof_steps):
-        step()
+        s.get("prof_step", step)()
     torch.cuda.synchronize()
     prof = H.prof_read()
     H.prof_enable(False)

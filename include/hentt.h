@@ -44,6 +44,7 @@ extern "C" {
 #define HENTT_EMODULUS (-2)  /* modulus not prime, not 1 mod 2N, or out of (2^7, 2^60) */
 #define HENTT_ENOMEM (-3)    /* host or device allocation failed */
 #define HENTT_EHIP (-4)      /* a HIP runtime call failed; see hentt_last_hip_error() */
+#define HENTT_ETIMEOUT (-5)  /* a persistent batch tile gave up waiting (reported by hentt_batch_plan_status) */
 
 #define HENTT_LOG_N_MIN 6
 #define HENTT_LOG_N_MAX 17
@@ -125,10 +126,36 @@ typedef struct {
 } hentt_job;
 
 /* Transforms every job (dir = +1 forward, -1 inverse), each job at its own N
- * and limb count, in a single persistent kernel launch (section III-B,
- * batch x RNS parallelism).  jobs is a HOST array; its contents are copied
- * before the call returns. */
+ * and limb count, in a single persistent kernel launch (section III-B: the
+ * batch and RNS limbs give independent transforms).  jobs is a HOST array; it
+ * is read before the call returns.  The first call with a given job list
+ * builds a plan (tile list on the device, synchronous) and caches it (up to
+ * 16 plans, keyed by pointers, shapes and direction); later calls only
+ * enqueue.  Jobs with N < 2^12 run as ordinary launches in the same call. */
 int hentt_ntt_batch(const hentt_job *jobs, uint32_t njobs, int dir, void *stream);
+
+/* Explicit plans for the same persistent launch (for autotuning and graphs).
+ * create: validates the jobs and uploads the tile list (synchronous).
+ * set_grid: number of persistent workgroups (0 = 4 per compute unit).
+ * run: enqueues a counter reset kernel and the persistent kernel on stream.
+ * status: waits for the last run; HENTT_ETIMEOUT if a pass-2 tile gave up
+ * waiting for its pass-1 tiles (bounded spin), else HENTT_OK.
+ * The job data stay owned by the caller and must outlive every run. */
+typedef struct hentt_batch_plan hentt_batch_plan;
+int hentt_batch_plan_create(const hentt_job *jobs, uint32_t njobs, int dir, hentt_batch_plan **out);
+int hentt_batch_plan_set_grid(hentt_batch_plan *p, uint32_t workgroups);
+int hentt_batch_plan_info(const hentt_batch_plan *p, uint32_t *units, uint32_t *tiles, uint32_t *grid);
+int hentt_batch_plan_run(hentt_batch_plan *p, void *stream);
+int hentt_batch_plan_status(hentt_batch_plan *p);
+int hentt_batch_plan_destroy(hentt_batch_plan *p);
+
+/* A plan's launch sequence captured once into a hipGraph (on a private
+ * stream; the counter reset is a kernel, not a memset node) and replayed with
+ * hentt_graph_launch on any stream. */
+typedef struct hentt_graph hentt_graph;
+int hentt_batch_graph_create(hentt_batch_plan *p, hentt_graph **out);
+int hentt_graph_launch(hentt_graph *g, void *stream);
+int hentt_graph_destroy(hentt_graph *g);
 
 /* Kernel timing for benchmarks.  While enabled, every kernel the library
  * launches is bracketed by HIP events recorded on the launching stream.

@@ -12,7 +12,7 @@ import os
 import torch
 
 __all__ = ["HenttError", "Tables", "ntt_fwd", "ntt_inv", "dyadic_mul", "polymul", "ct_tensor", "ntt_batch",
-           "psi", "lib", "LIB_PATH", "prof_enable", "prof_read"]
+           "psi", "lib", "LIB_PATH", "prof_enable", "prof_read", "BatchPlan"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhentt.so")
@@ -56,6 +56,15 @@ def lib():
             "hentt_ct_tensor": [_VP, _VP, _VP, _VP, _U32, _U32, _VP],
             "hentt_ntt_batch": [ctypes.POINTER(_Job), _U32, ctypes.c_int, _VP],
             "hentt_last_hip_error": [],
+            "hentt_batch_plan_create": [ctypes.POINTER(_Job), _U32, ctypes.c_int, ctypes.POINTER(_VP)],
+            "hentt_batch_plan_set_grid": [_VP, _U32],
+            "hentt_batch_plan_info": [_VP, ctypes.POINTER(_U32), ctypes.POINTER(_U32), ctypes.POINTER(_U32)],
+            "hentt_batch_plan_run": [_VP, _VP],
+            "hentt_batch_plan_status": [_VP],
+            "hentt_batch_plan_destroy": [_VP],
+            "hentt_batch_graph_create": [_VP, ctypes.POINTER(_VP)],
+            "hentt_graph_launch": [_VP, _VP],
+            "hentt_graph_destroy": [_VP],
             "hentt_prof_enable": [ctypes.c_int],
             "hentt_prof_count": [],
             "hentt_prof_get": [_U32, ctypes.c_char_p, _U32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_U32)],
@@ -229,10 +238,9 @@ def ct_tensor(tables, c, d, out=None, in_ntt=False, out_ntt=False, stream=None):
     return out
 
 
-def ntt_batch(jobs, direction, stream=None):
-    """Transform an uneven batch in one launch.  jobs: list of (x, tables, limbs)
-    with x [batch, limbs, N] for that tables' N; direction +1 or -1."""
+def _job_array(jobs):
     arr = (_Job * len(jobs))()
+    keep = []
     for i, (x, t, limbs) in enumerate(jobs):
         if x.shape[-1] != t.n or x.shape[-2] != limbs:
             raise HenttError("job %d: x must have shape [batch, limbs=%d, N=%d]" % (i, limbs, t.n))
@@ -240,4 +248,69 @@ def ntt_batch(jobs, direction, stream=None):
         arr[i].t = t.handle
         arr[i].limbs = limbs
         arr[i].batch = x.numel() // (limbs * t.n)
+        keep.append(x)
+    return arr
+
+
+class BatchPlan:
+    """A persistent-launch plan for an uneven batch (see hentt_batch_plan_*)."""
+
+    def __init__(self, jobs, direction):
+        self._keep = [(x, t) for x, t, _ in jobs]      # the plan holds raw pointers into these
+        arr = _job_array(jobs)
+        h = _VP()
+        _check(lib().hentt_batch_plan_create(arr, len(jobs), int(direction), ctypes.byref(h)), "plan_create")
+        self._h = h
+        self._graph = None
+
+    def info(self):
+        u, t, g = _U32(), _U32(), _U32()
+        _check(lib().hentt_batch_plan_info(self._h, ctypes.byref(u), ctypes.byref(t), ctypes.byref(g)), "plan_info")
+        return {"units": u.value, "tiles": t.value, "grid": g.value}
+
+    def set_grid(self, workgroups):
+        _check(lib().hentt_batch_plan_set_grid(self._h, int(workgroups)), "plan_set_grid")
+        self.drop_graph()
+
+    def run(self, stream=None):
+        _check(lib().hentt_batch_plan_run(self._h, _stream(stream)), "plan_run")
+
+    def status(self):
+        rc = lib().hentt_batch_plan_status(self._h)
+        _check(rc, "plan_status")
+
+    def capture(self):
+        """Capture the launch sequence into a hipGraph (replayed by replay())."""
+        self.drop_graph()
+        g = _VP()
+        _check(lib().hentt_batch_graph_create(self._h, ctypes.byref(g)), "graph_create")
+        self._graph = g
+
+    def replay(self, stream=None):
+        if self._graph is None:
+            self.capture()
+        _check(lib().hentt_graph_launch(self._graph, _stream(stream)), "graph_launch")
+
+    def drop_graph(self):
+        if self._graph is not None and _lib is not None:
+            lib().hentt_graph_destroy(self._graph)
+        self._graph = None
+
+    def close(self):
+        self.drop_graph()
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            lib().hentt_batch_plan_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ntt_batch(jobs, direction, stream=None):
+    """Transform an uneven batch in one launch.  jobs: list of (x, tables, limbs)
+    with x [batch, limbs, N] for that tables' N; direction +1 or -1."""
+    arr = _job_array(jobs)
     _check(lib().hentt_ntt_batch(arr, len(jobs), int(direction), _stream(stream)), "hentt_ntt_batch")

@@ -4,7 +4,9 @@
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#include <algorithm>
 #include <atomic>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
@@ -12,6 +14,7 @@
 
 #include "../../include/hentt.h"
 #include "ntt_kernels.hpp"
+#include "batch_kernels.hpp"
 
 using namespace hentt;
 
@@ -385,6 +388,7 @@ const char *hentt_status_str(int s) {
     case HENTT_EMODULUS: return "bad modulus (must be prime, 1 mod 2N, 2^7 < q < 2^60)";
     case HENTT_ENOMEM: return "out of memory";
     case HENTT_EHIP: return "HIP runtime error";
+    case HENTT_ETIMEOUT: return "a batch tile waited past its spin limit (results incomplete)";
     default: return "unknown status";
   }
 }
@@ -552,18 +556,321 @@ int hentt_ct_tensor(const hentt_tables *t, const uint64_t *c, const uint64_t *d,
   return run_prod(t, PROD_TENSOR, pa, batch, !(flags & HENTT_IN_NTT), !(flags & HENTT_OUT_NTT), (hipStream_t)stream);
 }
 
-int hentt_ntt_batch(const hentt_job *jobs, uint32_t njobs, int dir, void *stream) {
-  if (!jobs || njobs == 0 || (dir != 1 && dir != -1)) return HENTT_EINVAL;
+// ------------------------------------------------------------ uneven batches
+}  // extern "C"
+
+struct hentt_batch_plan {
+  int dir = 1;
+  int device = 0;
+  uint32_t nunits = 0, ntiles = 0, grid = 0, nq = 0;
+  std::vector<BatchUnit> units;          // host copy (queues are rebuilt when the grid changes)
+  BatchUnit *d_units = nullptr;
+  BatchTile *d_tiles = nullptr;
+  uint32_t *d_qoff = nullptr;            // BATCH_NQ + 1 tile offsets
+  uint32_t *d_qmap = nullptr;            // 16 entries: XCC_ID -> queue (or ~0)
+  uint32_t *d_ctl = nullptr;             // BATCH_NQ + 1 + nunits words
+  std::vector<uint32_t> qlen;
+  std::vector<hentt_job> small;          // jobs with N < 2^12: ordinary launches
+  std::vector<hentt_tables> small_views;
+  hipEvent_t done = nullptr;
+};
+
+struct hentt_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+const uint32_t kSpinLimit = 1u << 22;   // bounded wait of a pass-2 tile (s_sleep 4 per try)
+
+int default_grid() {
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  return cus * 2;  // the persistent kernel holds many VGPRs: 2 workgroups of 256 lanes per CU
+}
+
+void plan_free(hentt_batch_plan *p) {
+  if (p->done) (void)hipEventSynchronize(p->done), (void)hipEventDestroy(p->done);
+  for (void *d : {(void *)p->d_units, (void *)p->d_tiles, (void *)p->d_qoff, (void *)p->d_qmap, (void *)p->d_ctl})
+    if (d) (void)hipFree(d);
+  delete p;
+}
+
+uint32_t pass1_tiles(uint32_t ln, int dir) {
+  if (ln == BATCH_B) return 0;
+  return dir > 0 ? batch_col_tiles(ln) : (1u << (ln - BATCH_B));
+}
+uint32_t pass2_tiles(uint32_t ln, int dir) {
+  if (ln == BATCH_B) return 0;
+  return dir > 0 ? (1u << (ln - BATCH_B)) : batch_col_tiles(ln);
+}
+
+// Places the plan's workgroups (probe kernel), maps XCDs to queues, spreads
+// the units over the queues (largest first, least-loaded queue) and orders
+// each queue: pass 1 of the next D units runs ahead of pass 2.
+int plan_queues(hentt_batch_plan *p) {
+  const uint32_t grid = std::max(1u, p->grid);
+  uint32_t *d_probe = nullptr;
+  HIPCHK(hipMalloc(&d_probe, grid * sizeof(uint32_t)));
+  hipLaunchKernelGGL(k_xcc_probe, dim3(grid), dim3(64), 0, 0, d_probe);
+  std::vector<uint32_t> where(grid);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpy(where.data(), d_probe, grid * sizeof(uint32_t), hipMemcpyDeviceToHost);
+  (void)hipFree(d_probe);
+  if (e != hipSuccess) return hip_fail(e);
+  uint32_t qmap[16];
+  for (auto &m : qmap) m = ~0u;
+  uint32_t nq = 0;
+  for (uint32_t x : where)
+    if (qmap[x & 15] == ~0u && nq < BATCH_NQ) qmap[x & 15] = nq++;
+  p->nq = nq;
+  // cost of a unit ~ N log N
+  std::vector<uint32_t> order(p->units.size());
+  for (uint32_t i = 0; i < order.size(); ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return p->units[a].logn > p->units[b].logn; });
+  std::vector<std::vector<uint32_t>> qunits(nq);
+  std::vector<double> load(nq, 0.0);
+  for (uint32_t i : order) {
+    uint32_t best = 0;
+    for (uint32_t k = 1; k < nq; ++k)
+      if (load[k] < load[best]) best = k;
+    qunits[best].push_back(i);
+    load[best] += (double)(1u << p->units[i].logn) * p->units[i].logn;
+  }
+  std::vector<BatchTile> tiles;
+  std::vector<uint32_t> qoff(BATCH_NQ + 1, 0);
+  const uint32_t D = 4;
+  for (uint32_t k = 0; k < BATCH_NQ; ++k) {
+    qoff[k] = (uint32_t)tiles.size();
+    if (k >= nq) continue;
+    const std::vector<uint32_t> &us = qunits[k];
+    auto emit1 = [&](uint32_t i) {
+      const BatchUnit &u = p->units[i];
+      if (u.logn == BATCH_B) tiles.push_back({i, (uint32_t)BT_WHOLE << 16});
+      for (uint32_t t = 0; t < u.pass1; ++t) tiles.push_back({i, ((uint32_t)BT_PASS1 << 16) | t});
+    };
+    auto emit2 = [&](uint32_t i) {
+      const BatchUnit &u = p->units[i];
+      for (uint32_t t = 0; t < pass2_tiles(u.logn, p->dir); ++t) tiles.push_back({i, ((uint32_t)BT_PASS2 << 16) | t});
+    };
+    for (uint32_t j = 0; j < us.size() && j < D; ++j) emit1(us[j]);
+    for (uint32_t j = 0; j < us.size(); ++j) {
+      emit2(us[j]);
+      if (j + D < us.size()) emit1(us[j + D]);
+    }
+  }
+  qoff[BATCH_NQ] = (uint32_t)tiles.size();
+  p->ntiles = (uint32_t)tiles.size();
+  p->qlen.assign(BATCH_NQ, 0);
+  for (uint32_t k = 0; k < BATCH_NQ; ++k) p->qlen[k] = qoff[k + 1] - qoff[k];
+  if (p->d_tiles) (void)hipFree(p->d_tiles);
+  p->d_tiles = nullptr;
+  e = hipMalloc(&p->d_tiles, std::max<size_t>(1, tiles.size()) * sizeof(BatchTile));
+  if (e == hipSuccess && !tiles.empty())
+    e = hipMemcpy(p->d_tiles, tiles.data(), tiles.size() * sizeof(BatchTile), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->d_qoff, qoff.data(), qoff.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->d_qmap, qmap, sizeof(qmap), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e);
+  return HENTT_OK;
+}
+
+int plan_build(const hentt_job *jobs, uint32_t njobs, int dir, hentt_batch_plan **out) {
+  if (!jobs || njobs == 0 || !out || (dir != 1 && dir != -1)) return HENTT_EINVAL;
   for (uint32_t j = 0; j < njobs; ++j) {
     const hentt_job &jb = jobs[j];
     if (!jb.data || !jb.t || jb.batch == 0 || jb.limbs == 0 || jb.limbs > jb.t->limbs) return HENTT_EINVAL;
   }
+  hentt_batch_plan *p = new (std::nothrow) hentt_batch_plan();
+  if (!p) return HENTT_ENOMEM;
+  p->dir = dir;
+  (void)hipGetDevice(&p->device);
   for (uint32_t j = 0; j < njobs; ++j) {
-    hentt_tables v{jobs[j].t->s, jobs[j].limbs};
-    int rc = run_transform(&v, jobs[j].data, jobs[j].batch, (hipStream_t)stream, dir < 0);
+    const hentt_job &jb = jobs[j];
+    const uint32_t ln = jb.t->s->log_n;
+    const uint64_t N = 1ull << ln;
+    if (ln < BATCH_B) {
+      p->small.push_back(jb);
+      continue;
+    }
+    for (uint32_t b = 0; b < jb.batch; ++b)
+      for (uint32_t l = 0; l < jb.limbs; ++l) {
+        BatchUnit u;
+        u.data = jb.data + ((uint64_t)b * jb.limbs + l) * N;
+        u.tw = jb.t->s->d_tw + ((size_t)l * 2 + (dir < 0 ? 1 : 0)) * N;
+        u.lc = jb.t->s->d_lc + l;
+        u.logn = ln;
+        u.pass1 = pass1_tiles(ln, dir);
+        p->units.push_back(u);
+      }
+  }
+  for (auto &sj : p->small) p->small_views.push_back(hentt_tables{sj.t->s, sj.limbs});
+  p->nunits = (uint32_t)p->units.size();
+  p->grid = (uint32_t)default_grid();
+  hipError_t e = hipEventCreateWithFlags(&p->done, hipEventDisableTiming);
+  if (p->nunits && e == hipSuccess) {
+    e = hipMalloc(&p->d_units, p->units.size() * sizeof(BatchUnit));
+    if (e == hipSuccess) e = hipMalloc(&p->d_qoff, (BATCH_NQ + 1) * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(&p->d_qmap, 16 * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(&p->d_ctl, (BATCH_NQ + 1 + p->units.size()) * sizeof(uint32_t));
+    if (e == hipSuccess)
+      e = hipMemcpy(p->d_units, p->units.data(), p->units.size() * sizeof(BatchUnit), hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) {
+    plan_free(p);
+    g_last_hip = (int)e;
+    return e == hipErrorOutOfMemory ? HENTT_ENOMEM : HENTT_EHIP;
+  }
+  if (p->nunits) {
+    int rc = plan_queues(p);
+    if (rc) {
+      plan_free(p);
+      return rc;
+    }
+  }
+  *out = p;
+  return HENTT_OK;
+}
+
+int plan_launch(hentt_batch_plan *p, hipStream_t st) {
+  const int LOGN = 0;  // timer label
+  if (p->nunits) {
+    const uint32_t n = BATCH_NQ + 1 + p->nunits;
+    hipLaunchKernelGGL(k_fill_u32, dim3((n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024), dim3(256), 0, st, p->d_ctl, n, 0u);
+    HIPCHK(hipGetLastError());
+    const uint32_t grid = p->grid;  // every workgroup of the probed placement (idle ones exit at once)
+    if (p->dir > 0) { LaunchTimer lt_("k_batch_fwd", LOGN, st); hipLaunchKernelGGL(k_batch<false>, dim3(grid), dim3(BATCH_LANES), 0, st, p->d_units, p->d_tiles, p->d_qoff, p->d_qmap, p->d_ctl, kSpinLimit); }
+    else { LaunchTimer lt_("k_batch_inv", LOGN, st); hipLaunchKernelGGL(k_batch<true>, dim3(grid), dim3(BATCH_LANES), 0, st, p->d_units, p->d_tiles, p->d_qoff, p->d_qmap, p->d_ctl, kSpinLimit); }
+    HIPCHK(hipGetLastError());
+  }
+  for (size_t i = 0; i < p->small.size(); ++i) {
+    int rc = run_transform(&p->small_views[i], p->small[i].data, p->small[i].batch, st, p->dir < 0);
     if (rc) return rc;
   }
   return HENTT_OK;
+}
+
+// Plans made by hentt_ntt_batch, keyed by the job list (bounded cache).
+std::mutex g_plan_mu;
+std::map<std::vector<uint64_t>, hentt_batch_plan *> g_plans;
+
+}  // namespace
+
+extern "C" {
+
+int hentt_batch_plan_create(const hentt_job *jobs, uint32_t njobs, int dir, hentt_batch_plan **out) {
+  return plan_build(jobs, njobs, dir, out);
+}
+
+int hentt_batch_plan_set_grid(hentt_batch_plan *p, uint32_t workgroups) {
+  if (!p) return HENTT_EINVAL;
+  if (p->done) HIPCHK(hipEventSynchronize(p->done));
+  p->grid = workgroups ? workgroups : (uint32_t)default_grid();
+  return p->nunits ? plan_queues(p) : HENTT_OK;
+}
+
+int hentt_batch_plan_info(const hentt_batch_plan *p, uint32_t *units, uint32_t *tiles, uint32_t *grid) {
+  if (!p) return HENTT_EINVAL;
+  if (units) *units = p->nunits;
+  if (tiles) *tiles = p->ntiles;
+  if (grid) *grid = p->grid;
+  return HENTT_OK;
+}
+
+int hentt_batch_plan_run(hentt_batch_plan *p, void *stream) {
+  if (!p) return HENTT_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  int rc = plan_launch(p, st);
+  if (rc) return rc;
+  HIPCHK(hipEventRecord(p->done, st));
+  return HENTT_OK;
+}
+
+int hentt_batch_plan_status(hentt_batch_plan *p) {
+  if (!p) return HENTT_EINVAL;
+  if (!p->nunits) return HENTT_OK;
+  HIPCHK(hipEventSynchronize(p->done));
+  uint32_t h[BATCH_NQ + 1];
+  HIPCHK(hipMemcpy(h, p->d_ctl, sizeof(h), hipMemcpyDeviceToHost));
+  if (h[BATCH_NQ]) return HENTT_ETIMEOUT;
+  for (uint32_t k = 0; k < BATCH_NQ; ++k)
+    if (h[k] < p->qlen[k]) return HENTT_ETIMEOUT;  // a queue no workgroup served
+  return HENTT_OK;
+}
+
+int hentt_batch_plan_destroy(hentt_batch_plan *p) {
+  if (!p) return HENTT_EINVAL;
+  plan_free(p);
+  return HENTT_OK;
+}
+
+int hentt_batch_graph_create(hentt_batch_plan *p, hentt_graph **out) {
+  if (!p || !out) return HENTT_EINVAL;
+  hipStream_t cs = nullptr;
+  HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hentt_graph *g = new (std::nothrow) hentt_graph();
+  if (!g) {
+    (void)hipStreamDestroy(cs);
+    return HENTT_ENOMEM;
+  }
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  int rc = HENTT_OK;
+  if (e == hipSuccess) rc = plan_launch(p, cs);
+  hipError_t e2 = hipStreamEndCapture(cs, &g->graph);
+  if (e == hipSuccess) e = e2;
+  if (e == hipSuccess && !rc) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+  (void)hipStreamDestroy(cs);
+  if (e != hipSuccess || rc) {
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+    if (rc) return rc;
+    return hip_fail(e);
+  }
+  *out = g;
+  return HENTT_OK;
+}
+
+int hentt_graph_launch(hentt_graph *g, void *stream) {
+  if (!g) return HENTT_EINVAL;
+  HIPCHK(hipGraphLaunch(g->exec, (hipStream_t)stream));
+  return HENTT_OK;
+}
+
+int hentt_graph_destroy(hentt_graph *g) {
+  if (!g) return HENTT_EINVAL;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+  return HENTT_OK;
+}
+
+int hentt_ntt_batch(const hentt_job *jobs, uint32_t njobs, int dir, void *stream) {
+  if (!jobs || njobs == 0 || (dir != 1 && dir != -1)) return HENTT_EINVAL;
+  std::vector<uint64_t> key;
+  key.push_back((uint64_t)(int64_t)dir);
+  for (uint32_t j = 0; j < njobs; ++j) {
+    key.push_back((uint64_t)(uintptr_t)jobs[j].data);
+    key.push_back((uint64_t)(uintptr_t)jobs[j].t->s);
+    key.push_back(((uint64_t)jobs[j].limbs << 32) | jobs[j].batch);
+  }
+  hentt_batch_plan *p = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    auto it = g_plans.find(key);
+    if (it != g_plans.end()) p = it->second;
+  }
+  if (!p) {
+    int rc = plan_build(jobs, njobs, dir, &p);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    if (g_plans.size() >= 16) {  // evict one plan (waits for its last run)
+      plan_free(g_plans.begin()->second);
+      g_plans.erase(g_plans.begin());
+    }
+    g_plans[key] = p;
+  }
+  return hentt_batch_plan_run(p, stream);
 }
 
 int hentt_prof_enable(int on) {

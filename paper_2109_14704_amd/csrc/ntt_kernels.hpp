@@ -66,17 +66,17 @@ struct RoundMap {
 // ---------------------------------------------------------------- rounds --
 // Forward stages with global index s = LOGN - LO - R + u, u < R.  Stage s
 // pairs j with j + N/2^(s+1) and uses psi_rev[2^s + (j >> (LOGN - s))].
-template <int LOGN, int B, int E, int LO, int R>
-__device__ __forceinline__ void fwd_round(uint64_t (&x)[1 << E], uint32_t blockStart, uint32_t lanePart,
-                                          const Tw* __restrict__ tw, const ModQ &m) {
+template <int B, int E, int LO, int R>
+__device__ __forceinline__ void fwd_round(uint64_t (&x)[1 << E], uint32_t logn, uint32_t blockStart,
+                                          uint32_t lanePart, const Tw* __restrict__ tw, const ModQ &m) {
   using M = RoundMap<B, E, LO, R>;
 #pragma unroll
   for (int g = 0; g < (1 << (E - R)); ++g) {
     const uint32_t J0 = M::LANE_LOW ? (blockStart | M::g_part(g)) : (blockStart | lanePart | M::g_part(g));
 #pragma unroll
     for (int u = 0; u < R; ++u) {
-      const int s = LOGN - LO - R + u;
-      const uint32_t base = (1u << s) + (J0 >> (LO + R - u));
+      // stage s = logn - LO - R + u: 2^s = 2^(logn - B) * 2^(B - LO - R + u)
+      const uint32_t base = ((1u << (logn - B)) << (B - LO - R + u)) + (J0 >> (LO + R - u));
       const int h = 1 << (R - 1 - u);
 #pragma unroll
       for (int k = 0; k < (1 << R); ++k) {
@@ -91,9 +91,9 @@ __device__ __forceinline__ void fwd_round(uint64_t (&x)[1 << E], uint32_t blockS
 // Inverse stages v = LO + u.  Stage v pairs j with j + 2^v and uses
 // psi_rev^-1[N/2^(v+1) + (j >> (v+1))].  The last stage (v = LOGN-1) also
 // multiplies both outputs by N^-1.
-template <int LOGN, int B, int E, int LO, int R>
-__device__ __forceinline__ void inv_round(uint64_t (&x)[1 << E], uint32_t blockStart, uint32_t lanePart,
-                                          const Tw* __restrict__ itw, const LimbConst& c) {
+template <int B, int E, int LO, int R>
+__device__ __forceinline__ void inv_round(uint64_t (&x)[1 << E], uint32_t logn, uint32_t blockStart,
+                                          uint32_t lanePart, const Tw* __restrict__ itw, const LimbConst& c) {
   using M = RoundMap<B, E, LO, R>;
 #pragma unroll
   for (int g = 0; g < (1 << (E - R)); ++g) {
@@ -102,7 +102,8 @@ __device__ __forceinline__ void inv_round(uint64_t (&x)[1 << E], uint32_t blockS
     for (int u = 0; u < R; ++u) {
       const int v = LO + u;
       const int d = 1 << u;
-      if (v == LOGN - 1) {
+      // only the block's top stage can be the transform's last one
+      if (LO + u == B - 1 && (uint32_t)v == logn - 1) {
         // last stage: one group, twiddle psi^-brv(1) folded with N^-1
 #pragma unroll
         for (int k = 0; k < (1 << R); ++k) {
@@ -114,7 +115,7 @@ __device__ __forceinline__ void inv_round(uint64_t (&x)[1 << E], uint32_t blockS
           Y = shoup(c.ninvw, c.ninvw_s, df, c.m.nq);
         }
       } else {
-        const uint32_t base = (uint32_t)((1u << LOGN) >> (v + 1)) + (J0 >> (v + 1));
+        const uint32_t base = ((1u << logn) >> (v + 1)) + (J0 >> (v + 1));
 #pragma unroll
         for (int k = 0; k < (1 << R); ++k) {
           if (k & d) continue;
@@ -167,12 +168,12 @@ template <int E> __device__ __forceinline__ void reduce_inv(uint64_t (&x)[1 << E
 // [LO, LO+R)), starting from registers already loaded with the first round's
 // map.  Ends with the lane holding the last round (LO = 0) map in registers,
 // i.e. 2^E consecutive elements, values in [0, 4q).
-template <int LOGN, int B, int E, int LO, int R>
-__device__ __forceinline__ void fwd_block_rounds(uint64_t (&x)[1 << E], uint64_t* lds, uint32_t tid,
+template <int B, int E, int LO, int R>
+__device__ __forceinline__ void fwd_block_rounds(uint64_t (&x)[1 << E], uint32_t logn, uint64_t* lds, uint32_t tid,
                                                  uint32_t blockStart, const Tw* __restrict__ tw, const ModQ &m) {
   using M = RoundMap<B, E, LO, R>;
   const uint32_t lp = M::lane_part(tid);
-  fwd_round<LOGN, B, E, LO, R>(x, blockStart, lp, tw, m);
+  fwd_round<B, E, LO, R>(x, logn, blockStart, lp, tw, m);
   if constexpr (LO > 0) {
     constexpr int R2 = E;
     constexpr int LO2 = LO - R2;
@@ -181,20 +182,20 @@ __device__ __forceinline__ void fwd_block_rounds(uint64_t (&x)[1 << E], uint64_t
     __syncthreads();
     using M2 = RoundMap<B, E, LO2, R2>;
     load_lds<B, E, LO2, R2>(x, lds, M2::lane_part(tid));
-    fwd_block_rounds<LOGN, B, E, LO2, R2>(x, lds, tid, blockStart, tw, m);
+    fwd_block_rounds<B, E, LO2, R2>(x, logn, lds, tid, blockStart, tw, m);
   }
 }
 
 // Inverse rounds over block bits [LO, B), starting from registers loaded with
 // the (LO, R) map.  Ends with the lane holding the last round's map
 // (covering [B - Rlast, B)); values in [0, 2q).
-template <int LOGN, int B, int E, int LO, int R>
-__device__ __forceinline__ void inv_block_rounds(uint64_t (&x)[1 << E], uint64_t* lds, uint32_t tid,
+template <int B, int E, int LO, int R>
+__device__ __forceinline__ void inv_block_rounds(uint64_t (&x)[1 << E], uint32_t logn, uint64_t* lds, uint32_t tid,
                                                  uint32_t blockStart, const Tw* __restrict__ itw,
                                                  const LimbConst& c) {
   using M = RoundMap<B, E, LO, R>;
   const uint32_t lp = M::lane_part(tid);
-  inv_round<LOGN, B, E, LO, R>(x, blockStart, lp, itw, c);
+  inv_round<B, E, LO, R>(x, logn, blockStart, lp, itw, c);
   if constexpr (LO + R < B) {
     constexpr int LO2 = LO + R;
     constexpr int R2 = (B - LO2) < E ? (B - LO2) : E;
@@ -202,7 +203,7 @@ __device__ __forceinline__ void inv_block_rounds(uint64_t (&x)[1 << E], uint64_t
     __syncthreads();
     using M2 = RoundMap<B, E, LO2, R2>;
     load_lds<B, E, LO2, R2>(x, lds, M2::lane_part(tid));
-    inv_block_rounds<LOGN, B, E, LO2, R2>(x, lds, tid, blockStart, itw, c);
+    inv_block_rounds<B, E, LO2, R2>(x, logn, lds, tid, blockStart, itw, c);
   }
 }
 
@@ -246,7 +247,7 @@ __global__ __launch_bounds__(1 << (LOGN - E)) void k_fwd_whole(uint64_t* __restr
   using F = FwdFirst<LOGN, E>;
   uint64_t v[1 << E];
   load_global<LOGN, E, F::LO, F::R>(v, p, RoundMap<LOGN, E, F::LO, F::R>::lane_part(tid));
-  fwd_block_rounds<LOGN, LOGN, E, F::LO, F::R>(v, lds, tid, 0, t, m);
+  fwd_block_rounds<LOGN, E, F::LO, F::R>(v, LOGN, lds, tid, 0, t, m);
   reduce_fwd<E>(v, m);
   store_global<LOGN, E, 0, E>(v, p, RoundMap<LOGN, E, 0, E>::lane_part(tid));
 }
@@ -264,7 +265,7 @@ __global__ __launch_bounds__(1 << (LOGN - E)) void k_inv_whole(uint64_t* __restr
   using L = InvLast<LOGN, E>;
   uint64_t v[1 << E];
   load_global<LOGN, E, 0, E>(v, p, RoundMap<LOGN, E, 0, E>::lane_part(tid));
-  inv_block_rounds<LOGN, LOGN, E, 0, (LOGN < E ? LOGN : E)>(v, lds, tid, 0, it, c);
+  inv_block_rounds<LOGN, E, 0, (LOGN < E ? LOGN : E)>(v, LOGN, lds, tid, 0, it, c);
   reduce_inv<E>(v, c.m);
   store_global<LOGN, E, L::LO, L::R>(v, p, RoundMap<LOGN, E, L::LO, L::R>::lane_part(tid));
 }
@@ -299,10 +300,10 @@ __global__ __launch_bounds__(256) void k_cols(ColArgs a, const Tw *__restrict__ 
   load_global<LOGN, E, LO, E>(v, src, col);
   if constexpr (!INV) {
     const Tw *t = tw + (size_t)limb * 2 * (1u << LOGN);
-    fwd_round<LOGN, LOGN, E, LO, E>(v, 0, col, t, c.m);
+    fwd_round<LOGN, E, LO, E>(v, LOGN, 0, col, t, c.m);
   } else {
     const Tw *it = tw + ((size_t)limb * 2 + 1) * (1u << LOGN);
-    inv_round<LOGN, LOGN, E, LO, E>(v, 0, col, it, c);
+    inv_round<LOGN, E, LO, E>(v, LOGN, 0, col, it, c);
     reduce_inv<E>(v, c.m);
   }
   store_global<LOGN, E, LO, E>(v, dst, col);
@@ -325,7 +326,7 @@ __global__ __launch_bounds__(1 << (B - E)) void k_fwd_blocks(uint64_t *__restric
   using F = FwdFirst<B, E>;
   uint64_t v[1 << E];
   load_global<B, E, F::LO, F::R>(v, p, RoundMap<B, E, F::LO, F::R>::lane_part(tid));
-  fwd_block_rounds<LOGN, B, E, F::LO, F::R>(v, lds, tid, blockStart, t, m);
+  fwd_block_rounds<B, E, F::LO, F::R>(v, LOGN, lds, tid, blockStart, t, m);
   reduce_fwd<E>(v, m);
   store_global<B, E, 0, E>(v, p, RoundMap<B, E, 0, E>::lane_part(tid));
 }
@@ -346,7 +347,7 @@ __global__ __launch_bounds__(1 << (B - E)) void k_inv_blocks(uint64_t *__restric
   using L = InvLast<B, E>;
   uint64_t v[1 << E];
   load_global<B, E, 0, E>(v, p, RoundMap<B, E, 0, E>::lane_part(tid));
-  inv_block_rounds<LOGN, B, E, 0, E>(v, lds, tid, blockStart, it, c);
+  inv_block_rounds<B, E, 0, E>(v, LOGN, lds, tid, blockStart, it, c);
   store_global<B, E, L::LO, L::R>(v, p, RoundMap<B, E, L::LO, L::R>::lane_part(tid));
 }
 
@@ -441,7 +442,7 @@ __global__ __launch_bounds__(1 << (B - E)) void k_prod(ProdArgs a, const Tw *__r
       // from cache instead of being hoisted out of the loop into VGPRs
       const Tw *tp = opaque(t);
       load_global<B, E, F::LO, F::R>(v, a.in[p] + in_off, RoundMap<B, E, F::LO, F::R>::lane_part(tid));
-      fwd_block_rounds<LOGN, B, E, F::LO, F::R>(v, lds, tid, blockStart, tp, c.m);
+      fwd_block_rounds<B, E, F::LO, F::R>(v, LOGN, lds, tid, blockStart, tp, c.m);
       reduce_fwd<E>(v, c.m);
     } else {
       load_global<B, E, 0, E>(v, a.in[p] + in_off, M0::lane_part(tid));
@@ -470,7 +471,7 @@ __global__ __launch_bounds__(1 << (B - E)) void k_prod(ProdArgs a, const Tw *__r
     });
     if constexpr (DO_INV) {
       __syncthreads();  // earlier LDS reads of this workgroup are done
-      inv_block_rounds<LOGN, B, E, 0, E>(v, lds, tid, blockStart, opaque(it), c);
+      inv_block_rounds<B, E, 0, E>(v, LOGN, lds, tid, blockStart, opaque(it), c);
       if constexpr (B == LOGN) reduce_inv<E>(v, c.m);
       store_global<B, E, L::LO, L::R>(v, a.out[o] + out_off, RoundMap<B, E, L::LO, L::R>::lane_part(tid));
     } else {

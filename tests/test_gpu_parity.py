@@ -236,3 +236,80 @@ def test_repeat_determinism(gpu, log_n, pairs, limbs):
         assert int(got[-1, 1, -1, k]) == want
     nt = host(outs["ntt"][0])
     assert np.array_equal(nt, oracle.batch_tensor(c, d, mods))
+
+
+def _uneven_setup(gpu, njobs, seed_jobs=None):
+    import paper_2109_14704_amd as H
+    mods = workloads.moduli("uneven")
+    jobs = seed_jobs or workloads.uneven_jobs(njobs=njobs)
+    tables = {ln: H.Tables(ln, mods) for ln in sorted(set(ln for ln, _ in jobs))}
+    xs = [workloads.uneven_operand(j, ln, L, mods) for j, (ln, L) in enumerate(jobs)]
+    return H, mods, jobs, tables, xs
+
+
+def _check_uneven(xs, got, jobs, mods, direction):
+    for j, (ln, L) in enumerate(jobs):
+        g = host(got[j])
+        if (1 << ln) * L <= (1 << 16) * 3:
+            assert np.array_equal(g, oracle.batch_ntt(xs[j], mods[:L], direction)), j
+        else:
+            rng = np.random.default_rng(j)
+            for l in sorted({0, L - 1}):
+                for k in _sample_points(rng, 1 << ln, 2):
+                    f = oracle.ntt_fwd_point if direction > 0 else oracle.ntt_inv_point
+                    assert int(g[0, l, k]) == f(xs[j][0, l], mods[l], ln, k), (j, l, k)
+
+
+def test_batch_plan_all_sizes(gpu):
+    """Persistent launch over every N in 2^12..2^17 (plus N < 2^12 fallbacks), both directions."""
+    import torch
+    print("case batch plan all sizes", flush=True)
+    jobs = [(12, 3), (13, 2), (14, 1), (15, 2), (16, 1), (17, 2), (11, 2), (12, 1), (17, 1)]
+    H, mods, jobs, tables, xs = _uneven_setup(gpu, 0, jobs)
+    for direction in (+1, -1):
+        devs = [dev(x, gpu) for x in xs]
+        plan = H.BatchPlan([(d_, tables[ln], L) for d_, (ln, L) in zip(devs, jobs)], direction)
+        plan.run()
+        plan.status()
+        _check_uneven(xs, devs, jobs, mods, direction)
+        plan.close()
+        torch.cuda.synchronize()
+
+
+def test_batch_graph_replays_match_eager(gpu):
+    """hipGraph replays of the persistent launch equal eager runs, every replay."""
+    import torch
+    print("case batch graph replays", flush=True)
+    H, mods, jobs, tables, xs = _uneven_setup(gpu, 40)
+    devs = [dev(x, gpu) for x in xs]
+    plan = H.BatchPlan([(d_, tables[ln], L) for d_, (ln, L) in zip(devs, jobs)], +1)
+    plan.run()
+    plan.status()
+    eager = [d_.clone() for d_ in devs]
+    _check_uneven(xs, eager, jobs, mods, +1)
+    plan.capture()
+    for rep in range(3):
+        for d_, x in zip(devs, xs):
+            d_.copy_(dev(x, gpu))
+        torch.cuda.synchronize()
+        plan.replay()
+        plan.status()
+        torch.cuda.synchronize()
+        for a, b in zip(devs, eager):
+            assert torch.equal(a, b), rep
+    plan.close()
+
+
+@pytest.mark.parametrize("grid", [1, 7, 256, 2048])
+def test_batch_grid_sizes(gpu, grid):
+    """Any persistent grid size gives the same words (load balance only)."""
+    import torch
+    print("case batch grid %d" % grid, flush=True)
+    H, mods, jobs, tables, xs = _uneven_setup(gpu, 12)
+    devs = [dev(x, gpu) for x in xs]
+    plan = H.BatchPlan([(d_, tables[ln], L) for d_, (ln, L) in zip(devs, jobs)], +1)
+    plan.set_grid(grid)
+    plan.run()
+    plan.status()
+    _check_uneven(xs, devs, jobs, mods, +1)
+    plan.close()
