@@ -29,7 +29,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="ckks_level", choices=["ckks_level", "ct_tensor", "plain4096", "uneven"])
+    ap.add_argument("--workload", default="ckks_level",
+                    choices=["ckks_level", "ct_tensor", "plain4096", "uneven", "serving"])
+    ap.add_argument("--requests", type=int, default=2200, help="serving: requests per trace (first 200 warm up)")
     ap.add_argument("--grid", type=int, default=0, help="persistent workgroups for the uneven batch (0 = tuned/default)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-per-poly", action="store_true", help="skip the per-polynomial comparator")
@@ -273,8 +275,79 @@ def roofline(prof, info, steps):
     return rl, name, per_launch_s
 
 
+def bench_serving(args):
+    """Poisson ct-mul serving: saturation throughput, then p50/p99 latency of the
+    continuous-batching server and of per-request launches on the same traces
+    at 0.5, 0.8 and 0.95 of the server's saturation rate."""
+    import torch
+    import workloads
+    from paper_2109_14704_amd import serve
+    chain = workloads.moduli("serving")
+    be = serve.HipBackend(chain, streams=2)
+    gen = torch.Generator(device="cuda:0")
+    ops = {}
+
+    def operands(ln, lvl, k):
+        key = (ln, lvl, k)
+        if key not in ops:          # seeded, uniform per limb, device-resident
+            gen.manual_seed(2109_14704 + 4 * 1000003 + ln * 1009 + lvl * 31 + k)
+            c = torch.empty((1, 2, lvl, 1 << ln), dtype=torch.int64, device="cuda:0")
+            d = torch.empty_like(c)
+            for l in range(lvl):
+                c[:, :, l].random_(0, chain[l], generator=gen)
+                d[:, :, l].random_(0, chain[l], generator=gen)
+            ops[key] = (c, d)
+        return ops[key]
+
+    def requests(trace):
+        return [serve.Request(i, t, ln, lvl, *operands(ln, lvl, i % 2)) for i, (t, ln, lvl) in enumerate(trace)]
+
+    budget = 24 << 30
+    warm = 200
+    n = args.requests
+    # saturation: every request offered at t = 0
+    sat_trace = [(0.0, ln, lvl) for _, ln, lvl in workloads.serving_trace(n, 1.0, seed_stream=2)]
+    reqs = requests(sat_trace)
+    sched = serve.Scheduler(be, budget, streams=2)
+    sched.run_trace(reqs[:warm])
+    torch.cuda.synchronize()
+    reqs = requests(sat_trace)
+    sched = serve.Scheduler(be, budget, streams=2)
+    el = sched.run_trace(reqs)
+    sat = n / el
+    print("bench: serving saturation %.0f ct-mul/s (%d steps)" % (sat, sched.steps), file=sys.stderr, flush=True)
+    rows = []
+    for f in (0.5, 0.8, 0.95):
+        trace = workloads.serving_trace(n, f * sat, seed_stream=1)
+        rs = requests(trace)
+        sched = serve.Scheduler(be, budget, streams=2)
+        el = sched.run_trace(rs)
+        srv = serve.latency_stats(rs[warm:])
+        srv["throughput"] = round(len(rs) / el, 1)
+        rb = requests(trace)
+        elb = serve.serve_per_request(rb, be)
+        base = serve.latency_stats(rb[warm:])
+        base["throughput"] = round(len(rb) / elb, 1)
+        rows.append({"load": f, "rate_per_s": round(f * sat, 1), "server": srv, "per_request": base})
+        print("bench: load %.2f server p50 %.3f p99 %.3f ms; per-request p50 %.3f p99 %.3f ms" % (
+            f, srv.get("p50_ms", -1), srv.get("p99_ms", -1), base.get("p50_ms", -1), base.get("p99_ms", -1)),
+            file=sys.stderr, flush=True)
+    result = {"metric": METRIC, "value": round(sat, 1), "unit": "ct-mul/s", "n_gpus": 1, "steps": n,
+              "warmup": warm, "ms_per_step": round(1e3 / sat, 4), "higher_is_better": True, "scaling": "weak",
+              "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+              "config": {"workload": "serving", "N": [1 << 14, 1 << 15, 1 << 16], "levels": [4, 24],
+                         "hbm_budget_bytes": budget, "streams": 2, "requests": n},
+              "latency": rows}
+    print(json.dumps(result), flush=True)
+
+
 def main():
     args = parse()
+    if args.workload == "serving":
+        if args.gpus != 1:
+            print("bench.py: one GPU only", file=sys.stderr)
+            sys.exit(2)
+        return bench_serving(args)
     if args.gpus != 1:
         print("bench.py: this build measures one GPU; --gpus %d is not supported (the path shards by batch "
               "with no exchange, see the design notes)" % args.gpus, file=sys.stderr)

@@ -1,0 +1,45 @@
+"""GPU test of the serving path: requests of mixed N and level served with
+continuous batching give, word for word, the result of the same request run
+alone, and agree with the oracle on sampled coefficients."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def test_served_results_match_alone_and_oracle(gpu):
+    import torch
+    import paper_2109_14704_amd as H
+    from paper_2109_14704_amd import serve
+    print("case serving mix", flush=True)
+    chain = workloads.moduli("serving")
+    be = serve.HipBackend(chain, streams=2, verify=True)
+    trace = workloads.serving_trace(36, rate_per_s=3000.0, seed_stream=7)
+    reqs, host_ops = [], {}
+    for i, (t, ln, lvl) in enumerate(trace):
+        lvl = 4 + lvl % 9                      # keep the test small: levels 4..12
+        c, d = workloads.serving_operands(i, ln, lvl, chain)
+        host_ops[i] = (c, d)
+        reqs.append(serve.Request(i, t, ln, lvl, torch.from_numpy(c.view(np.int64)).cuda(),
+                                  torch.from_numpy(d.view(np.int64)).cuda()))
+    sched = serve.Scheduler(be, budget_bytes=serve.footprint(16, 12) * 6, streams=2)
+    sched.run_trace(reqs)
+    torch.cuda.synchronize()
+    assert all(r.state == "done" for r in reqs), [(r.rid, r.state, r.error) for r in reqs if r.state != "done"]
+    assert sched.steps >= 2 and sched.reserved == 0
+    for r in reqs:
+        alone = H.ct_tensor(be.view(r.log_n, r.level), r.c, r.d)
+        assert torch.equal(alone, r.result), r.rid
+    rng = np.random.default_rng(3)
+    for r in reqs[:4]:
+        c, d = host_ops[r.rid]
+        got = r.result.cpu().numpy().view(np.uint64)
+        l = int(rng.integers(0, r.level))
+        q = chain[l]
+        k = int(rng.integers(0, 1 << r.log_n))
+        want = (oracle.negacyclic_point(c[0, 0, l], d[0, 1, l], q, k)
+                + oracle.negacyclic_point(c[0, 1, l], d[0, 0, l], q, k)) % q
+        assert int(got[0, 1, l, k]) == want
