@@ -202,31 +202,33 @@ def cpu_baseline(s, target_s):
 
 
 # ---------------------------------------------------------------- roofline
-# 32-bit multiplies per unit of work (the algorithmic ALU count):
-MUL_BFLY = 10    # Shoup butterfly: hi64(W'Y) 4, lo64(WY) 3, lo64(Qq) 3
-MUL_PROD = 11    # Barrett product: 128-bit product 4, hi(z1 mu) 4, lo(q3 q) 3
-MUL_TENSOR = 37  # c0d0, c0d1 + c1d0, c1d1: four 128-bit products (16) + three reductions (21)
+# Algorithmic ALU work in VALU lane-operations (gfx950 has no 64-bit
+# multiplier; v_mad_u64_u32 / v_mul_hi_u32 / v_mul_lo_u32 issue at full rate, so
+# every VALU op costs one issue slot):
+VALU_BFLY = 21     # Harvey/Shoup butterfly: 9 32-bit multiplies + 12 adds, compares, selects
+VALU_PROD = 38     # Barrett product a*b mod q: 128-bit product, quotient estimate, 3 corrections
+VALU_TENSOR = 121  # c0d0, c1d1 (2 x 38) + c0d1 + c1d0 with one reduction (45)
 
 
 def kernel_work(name, info):
-    """Algorithmic HBM bytes and 32-bit multiplies of ONE launch of `name` in
+    """Algorithmic HBM bytes and VALU operations of ONE launch of `name` in
     the benchmarked step: per-unit figures times the units one launch handles.
     Bytes: every coefficient word a launch must read once and write once
-    (8 B each).  Multiplies: MUL_BFLY per butterfly, N/2 butterflies per
-    stage per polynomial limb, plus the products."""
+    (8 B each).  ALU: VALU_BFLY per butterfly, N/2 butterflies per stage per
+    polynomial limb, plus the products."""
     n, L = info["N"], info["limbs"]
     logn = n.bit_length() - 1
     ec = {13: 1, 14: 2, 15: 3, 16: 4, 17: 4}.get(logn, 0)    # stages in the column pass
     if info["workload"] == "ckks_level":
         p = info["polys_per_operand"]
-        n_in, n_out, prod_mul = 2 * p, p, MUL_PROD * p * L * n
+        n_in, n_out, prod_mul = 2 * p, p, VALU_PROD * p * L * n
     elif info["workload"] == "ct_tensor":
         c = info["ct_pairs"]
-        n_in, n_out, prod_mul = 4 * c, 3 * c, MUL_TENSOR * c * L * n
+        n_in, n_out, prod_mul = 4 * c, 3 * c, VALU_TENSOR * c * L * n
     else:
         n_in = n_out = info["polys"]
         prod_mul = 0
-    bfly = lambda polys, stages: MUL_BFLY * polys * L * (n // 2) * stages
+    bfly = lambda polys, stages: VALU_BFLY * polys * L * (n // 2) * stages
     base = name.split("<")[0]
     if base == "k_cols_fwd":
         return 16.0 * n_in * L * n, bfly(n_in, ec)
@@ -245,7 +247,7 @@ def batch_work(info, jobs):
     N = 2^12 is read and written once, larger N twice (two passes); butterflies
     (N/2) log2 N per (polynomial, limb)."""
     nbytes = sum(L * (1 << ln) * (16 if ln == 12 else 32) for ln, L in jobs)
-    muls = sum(MUL_BFLY * L * (1 << (ln - 1)) * ln for ln, L in jobs)
+    muls = sum(VALU_BFLY * L * (1 << (ln - 1)) * ln for ln, L in jobs)
     return float(nbytes), float(muls)
 
 
@@ -270,7 +272,7 @@ def roofline(prof, info, steps):
     else:
         ach = muls / per_launch_s / 1e12
         rl = {"bound": "alu", "achieved": round(ach, 3), "peak": round(R.VALU_PEAK_TOPS, 2),
-              "unit": "T int32-mul/s", "frac": round(ach / R.VALU_PEAK_TOPS, 4)}
+              "unit": "T VALU-op/s", "frac": round(ach / R.VALU_PEAK_TOPS, 4)}
     rl.update({"kernel": name, "launch_ms": round(per_launch_s * 1e3, 4), "traffic": R.stored_traffic(name)})
     return rl, name, per_launch_s
 
