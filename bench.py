@@ -216,9 +216,10 @@ def kernel_work(name, info):
     Bytes: every coefficient word a launch must read once and write once
     (8 B each).  ALU: VALU_BFLY per butterfly, N/2 butterflies per stage per
     polynomial limb, plus the products."""
+    import paper_2109_14704_amd as H
     n, L = info["N"], info["limbs"]
     logn = n.bit_length() - 1
-    ec = {13: 1, 14: 2, 15: 3, 16: 4, 17: 4}.get(logn, 0)    # stages in the column pass
+    t_cols, p_cols = H.stage_split(logn)                   # stages in the column passes (library plan)
     if info["workload"] == "ckks_level":
         p = info["polys_per_operand"]
         n_in, n_out, prod_mul = 2 * p, p, VALU_PROD * p * L * n
@@ -230,6 +231,7 @@ def kernel_work(name, info):
         prod_mul = 0
     bfly = lambda polys, stages: VALU_BFLY * polys * L * (n // 2) * stages
     base = name.split("<")[0]
+    ec = p_cols if info["workload"] in ("ckks_level", "ct_tensor") else t_cols
     if base == "k_cols_fwd":
         return 16.0 * n_in * L * n, bfly(n_in, ec)
     if base == "k_cols_inv":

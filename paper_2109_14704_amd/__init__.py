@@ -12,10 +12,10 @@ import os
 import torch
 
 __all__ = ["HenttError", "Tables", "ntt_fwd", "ntt_inv", "dyadic_mul", "polymul", "ct_tensor", "ntt_batch",
-           "psi", "lib", "LIB_PATH", "prof_enable", "prof_read", "BatchPlan"]
+           "psi", "lib", "LIB_PATH", "prof_enable", "prof_read", "BatchPlan", "stage_split"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libhentt.so")
+LIB_PATH = os.environ.get("HENTT_LIB") or os.path.join(_HERE, "libhentt.so")  # HENTT_LIB: alternative build
 
 HENTT_IN_NTT = 1
 HENTT_OUT_NTT = 2
@@ -65,6 +65,7 @@ def lib():
             "hentt_batch_graph_create": [_VP, ctypes.POINTER(_VP)],
             "hentt_graph_launch": [_VP, _VP],
             "hentt_graph_destroy": [_VP],
+            "hentt_stage_split": [_U32, ctypes.POINTER(_U32), ctypes.POINTER(_U32)],
             "hentt_prof_enable": [ctypes.c_int],
             "hentt_prof_count": [],
             "hentt_prof_get": [_U32, ctypes.c_char_p, _U32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_U32)],
@@ -124,6 +125,13 @@ def prof_read():
         _check(L.hentt_prof_get(i, buf, 128, ctypes.byref(ms), ctypes.byref(cnt)), "hentt_prof_get")
         out[buf.value.decode()] = (ms.value, cnt.value)
     return out
+
+
+def stage_split(log_n):
+    """(column stages of a plain transform, column stages of a fused product); 0 = whole."""
+    a, b = _U32(), _U32()
+    _check(lib().hentt_stage_split(log_n, ctypes.byref(a), ctypes.byref(b)), "hentt_stage_split")
+    return a.value, b.value
 
 
 def psi(q, log_n):

@@ -223,14 +223,30 @@ namespace {
 // Stage split per N: transforms with N <= 2^14 run whole in one workgroup
 // (one HBM round trip); larger N run a column pass of EC stages then blocks
 // of 2^(log_n - EC) coefficients.
+#ifndef HENTT_EC15
+#define HENTT_EC15 5
+#endif
+#ifndef HENTT_EC16
+#define HENTT_EC16 5
+#endif
+#ifndef HENTT_PEC15
+#define HENTT_PEC15 5
+#endif
+#ifndef HENTT_PEC16
+#define HENTT_PEC16 5
+#endif
+// Stage split (measured): the column pass is HBM-bound with idle ALU, so it
+// takes 5 stages at N = 2^15 and 2^16, leaving 2^10 / 2^11 blocks to the
+// ALU-bound block and fused kernels (the 5-stage split was 10% faster on the
+// CKKS-level batch and 19% on the ciphertext tensor than 3 / 4 stages).
 template <int LOGN> struct Plan {
   static constexpr bool WHOLE = LOGN <= 14;
-  static constexpr int EC = LOGN <= 15 ? (LOGN - 12 > 0 ? LOGN - 12 : 1) : (LOGN == 16 ? 4 : 4);
+  static constexpr int EC = LOGN == 15 ? HENTT_EC15 : LOGN == 16 ? HENTT_EC16 : LOGN == 17 ? 4 : (LOGN > 12 ? LOGN - 12 : 1);
   static constexpr int B = LOGN - EC;
   // fused products: one kernel up to 2^12, else a column pass of PEC stages
-  // and blocks of 2^12 coefficients
+  // and blocks of 2^(LOGN - PEC) coefficients
   static constexpr bool PROD_WHOLE = LOGN <= 12;
-  static constexpr int PEC = LOGN > 12 ? LOGN - 12 : 1;
+  static constexpr int PEC = LOGN == 15 ? HENTT_PEC15 : LOGN == 16 ? HENTT_PEC16 : (LOGN > 12 ? LOGN - 12 : 1);
 };
 // Elements per lane (2^E) in the fused product kernels: the tensor keeps four
 // transformed inputs live, so it uses 8 per lane to stay within the VGPRs.
@@ -283,6 +299,17 @@ void launch_inv(const hentt_tables *t, uint64_t *x, uint32_t batch, hipStream_t 
 // outputs go back to the coefficient domain.  ws: workspace for the forward
 // column pass output when the product is not one kernel (NIN components of
 // batch * limbs * N words), may be null otherwise.
+// HENTT_PROD_LDS: extra dynamic LDS bytes per fused-product workgroup (caps
+// its occupancy so other kernels' waves can share the CU; tuning knob).
+int g_prod_lds = -1;
+uint32_t prod_lds_pad() {
+  if (g_prod_lds < 0) {
+    const char *e = getenv("HENTT_PROD_LDS");
+    g_prod_lds = e ? atoi(e) : 0;
+  }
+  return (uint32_t)g_prod_lds;
+}
+
 template <int LOGN, int MODE>
 void launch_prod(const hentt_tables *t, const ProdArgs &pa, uint32_t batch, bool in_coeff, bool out_coeff,
                  uint64_t *ws, hipStream_t st) {
@@ -300,9 +327,9 @@ void launch_prod(const hentt_tables *t, const ProdArgs &pa, uint32_t batch, bool
   constexpr int PE = ProdE<MODE>::E;
   if constexpr (P::PROD_WHOLE) {
     const dim3 g(units), blk(1 << (LOGN - PE));
-    if (in_coeff && out_coeff) { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, LOGN, PE, MODE, true, true>), g, blk, 0, st, pa, tw, lc, batch, L); }
-    else if (in_coeff) { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, LOGN, PE, MODE, true, false>), g, blk, 0, st, pa, tw, lc, batch, L); }
-    else { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, LOGN, PE, MODE, false, true>), g, blk, 0, st, pa, tw, lc, batch, L); }
+    if (in_coeff && out_coeff) { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, LOGN, PE, MODE, true, true>), g, blk, prod_lds_pad(), st, pa, tw, lc, batch, L); }
+    else if (in_coeff) { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, LOGN, PE, MODE, true, false>), g, blk, prod_lds_pad(), st, pa, tw, lc, batch, L); }
+    else { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, LOGN, PE, MODE, false, true>), g, blk, prod_lds_pad(), st, pa, tw, lc, batch, L); }
   } else {
     constexpr int EC = P::PEC, B = LOGN - P::PEC;
     const uint64_t NL = (uint64_t)L << LOGN;
@@ -322,9 +349,9 @@ void launch_prod(const hentt_tables *t, const ProdArgs &pa, uint32_t batch, bool
                          ca, tw, lc, batch, L); }
     }
     const dim3 g(units << (LOGN - B)), blk(1 << (B - PE));
-    if (in_coeff && out_coeff) { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, B, PE, MODE, true, true>), g, blk, 0, st, pb, tw, lc, batch, L); }
-    else if (in_coeff) { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, B, PE, MODE, true, false>), g, blk, 0, st, pb, tw, lc, batch, L); }
-    else { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, B, PE, MODE, false, true>), g, blk, 0, st, pb, tw, lc, batch, L); }
+    if (in_coeff && out_coeff) { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, B, PE, MODE, true, true>), g, blk, prod_lds_pad(), st, pb, tw, lc, batch, L); }
+    else if (in_coeff) { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, B, PE, MODE, true, false>), g, blk, prod_lds_pad(), st, pb, tw, lc, batch, L); }
+    else { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, B, PE, MODE, false, true>), g, blk, prod_lds_pad(), st, pb, tw, lc, batch, L); }
     if (out_coeff) {
       ColArgs ca{};
       for (int o = 0; o < NOUT; ++o) ca.src[o] = ca.dst[o] = pa.out[o];
@@ -352,30 +379,154 @@ const prod_fn k_mul_table[] = {HENTT_SIZES(MUL_ENTRY)};
 const prod_fn k_ten_table[] = {HENTT_SIZES(TEN_ENTRY)};
 const bool k_ws_table[] = {HENTT_SIZES(WS_ENTRY)};
 
+// Two library streams per device (default priority) and a ring of events.
+// A large two-pass call is split into batch chunks alternating between the
+// two streams, so one chunk's HBM-bound column pass overlaps another chunk's
+// ALU-bound block kernel.  fork/join keep the caller's stream order: the
+// chunks wait on an event recorded on the caller's stream, and the caller's
+// stream waits on both library streams afterwards (no host synchronisation).
+struct DevStreams {
+  int device = -1;
+  hipStream_t s[2] = {nullptr, nullptr};
+  hipEvent_t ev[64] = {};
+  uint32_t next = 0;
+};
+std::mutex g_ds_mu;
+std::vector<DevStreams *> g_ds;
+
+DevStreams *dev_streams() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(g_ds_mu);
+  for (auto *d : g_ds)
+    if (d->device == dev) return d;
+  DevStreams *d = new (std::nothrow) DevStreams();
+  if (!d) return nullptr;
+  d->device = dev;
+  for (auto &x : d->s)
+    if (hipStreamCreateWithFlags(&x, hipStreamNonBlocking) != hipSuccess) return nullptr;
+  for (auto &e : d->ev)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+  g_ds.push_back(d);
+  return d;
+}
+
+hipEvent_t next_event(DevStreams *d) {
+  std::lock_guard<std::mutex> lk(g_ds_mu);
+  return d->ev[d->next++ % 64];
+}
+
+// Number of chunks for a two-pass call over batch x limbs (polynomial, limb)
+// pairs; HENTT_CHUNKS overrides it (tuning).
+int g_chunks_env = -2;
+uint32_t chunks_for(uint32_t batch, uint32_t limbs) {
+  if (g_chunks_env == -2) {
+    const char *e = getenv("HENTT_CHUNKS");
+    g_chunks_env = e ? atoi(e) : -1;
+  }
+  const uint64_t units = (uint64_t)batch * limbs;
+  uint32_t n = 1;  // chunking measured at most 2-5% faster: off unless requested
+  (void)units;
+  if (g_chunks_env > 0) n = (uint32_t)g_chunks_env;
+  return n > batch ? batch : n;
+}
+int g_streams_env = -2;
+int stream_count() {
+  if (g_streams_env == -2) {
+    const char *e = getenv("HENTT_STREAMS");
+    g_streams_env = e ? atoi(e) : 2;
+  }
+  return g_streams_env == 1 ? 1 : 2;
+}
+
+int fork_streams(DevStreams *d, hipStream_t caller) {
+  hipEvent_t e = next_event(d);
+  HIPCHK(hipEventRecord(e, caller));
+  HIPCHK(hipStreamWaitEvent(d->s[0], e, 0));
+  HIPCHK(hipStreamWaitEvent(d->s[1], e, 0));
+  return HENTT_OK;
+}
+
+int join_streams(DevStreams *d, hipStream_t caller) {
+  for (int k = 0; k < 2; ++k) {
+    hipEvent_t e = next_event(d);
+    HIPCHK(hipEventRecord(e, d->s[k]));
+    HIPCHK(hipStreamWaitEvent(caller, e, 0));
+  }
+  return HENTT_OK;
+}
+
 int run_transform(const hentt_tables *t, uint64_t *x, uint32_t batch, hipStream_t st, bool inv) {
   const int ln = (int)t->s->log_n;
-  (inv ? k_inv_table : k_fwd_table)[ln - HENTT_LOG_N_MIN](t, x, batch, st);
+  launch_fn fn = (inv ? k_inv_table : k_fwd_table)[ln - HENTT_LOG_N_MIN];
+  const uint32_t nch = ln > 14 ? chunks_for(batch, t->limbs) : 1;
+  DevStreams *d = nch > 1 ? dev_streams() : nullptr;
+  if (!d) {
+    fn(t, x, batch, st);
+    HIPCHK(hipGetLastError());
+    return HENTT_OK;
+  }
+  int rc = fork_streams(d, st);
+  if (rc) return rc;
+  const uint64_t NL = (uint64_t)t->limbs << ln;
+  for (uint32_t c = 0, b0 = 0; c < nch; ++c) {
+    const uint32_t b1 = (uint32_t)((uint64_t)batch * (c + 1) / nch);
+    fn(t, x + (uint64_t)b0 * NL, b1 - b0, d->s[stream_count() == 1 ? 0 : (c & 1)]);
+    b0 = b1;
+  }
   HIPCHK(hipGetLastError());
-  return HENTT_OK;
+  return join_streams(d, st);
 }
 
 int run_prod(const hentt_tables *t, int mode, const ProdArgs &pa, uint32_t batch, bool in_coeff, bool out_coeff,
              hipStream_t st) {
   const int ln = (int)t->s->log_n;
   const int nin = mode == PROD_MUL ? 2 : 4;
+  const uint64_t NL = (uint64_t)t->limbs << ln;
   void *ws = nullptr;
   if (in_coeff && k_ws_table[ln - HENTT_LOG_N_MIN]) {
-    int rc = pool_get((size_t)nin * batch * t->limbs * 8ull << ln, st, &ws);
+    int rc = pool_get((size_t)nin * batch * NL * 8ull, st, &ws);
     if (rc) return rc;
   }
-  (mode == PROD_MUL ? k_mul_table : k_ten_table)[ln - HENTT_LOG_N_MIN](t, pa, batch, in_coeff, out_coeff,
-                                                                       (uint64_t *)ws, st);
+  prod_fn fn = (mode == PROD_MUL ? k_mul_table : k_ten_table)[ln - HENTT_LOG_N_MIN];
+  const bool two_pass = k_ws_table[ln - HENTT_LOG_N_MIN] && (in_coeff || out_coeff);
+  const uint32_t nch = two_pass ? chunks_for(batch, t->limbs) : 1;
+  DevStreams *d = nch > 1 ? dev_streams() : nullptr;
+  int rc = HENTT_OK;
+  if (!d) {
+    fn(t, pa, batch, in_coeff, out_coeff, (uint64_t *)ws, st);
+  } else {
+    rc = fork_streams(d, st);
+    for (uint32_t c = 0, b0 = 0; c < nch && !rc; ++c) {
+      const uint32_t b1 = (uint32_t)((uint64_t)batch * (c + 1) / nch);
+      ProdArgs pc = pa;
+      for (int p = 0; p < nin; ++p) pc.in[p] = pa.in[p] + (uint64_t)b0 * pa.in_sb;
+      for (int o = 0; o < 3; ++o)
+        if (pa.out[o]) pc.out[o] = pa.out[o] + (uint64_t)b0 * pa.out_sb;
+      // each chunk owns the slice [chunk][batch entries][limbs][N] of the workspace
+      uint64_t *wc = ws ? (uint64_t *)ws + (uint64_t)nin * b0 * NL : nullptr;
+      fn(t, pc, b1 - b0, in_coeff, out_coeff, wc, d->s[stream_count() == 1 ? 0 : (c & 1)]);
+      b0 = b1;
+    }
+    if (!rc) rc = join_streams(d, st);
+  }
   hipError_t e = hipGetLastError();
   if (ws) pool_put(ws);
+  if (rc) return rc;
   if (e != hipSuccess) return hip_fail(e);
   return HENTT_OK;
 }
 
+}  // namespace
+
+namespace {
+template <int LOGN> void split_of(uint32_t *ec, uint32_t *pec) {
+  *ec = Plan<LOGN>::WHOLE ? 0u : (uint32_t)Plan<LOGN>::EC;
+  *pec = Plan<LOGN>::PROD_WHOLE ? 0u : (uint32_t)Plan<LOGN>::PEC;
+}
+typedef void (*split_fn)(uint32_t *, uint32_t *);
+#define SPLIT_ENTRY(n) split_of<n>,
+const split_fn k_split_table[] = {HENTT_SIZES(SPLIT_ENTRY)};
 }  // namespace
 
 // ================================================================== C ABI
@@ -394,6 +545,12 @@ const char *hentt_status_str(int s) {
 }
 
 int hentt_last_hip_error(void) { return g_last_hip; }
+
+int hentt_stage_split(uint32_t log_n, uint32_t *transform_cols, uint32_t *product_cols) {
+  if (!transform_cols || !product_cols || log_n < HENTT_LOG_N_MIN || log_n > HENTT_LOG_N_MAX) return HENTT_EINVAL;
+  k_split_table[log_n - HENTT_LOG_N_MIN](transform_cols, product_cols);
+  return HENTT_OK;
+}
 
 int hentt_psi(uint64_t q, uint32_t log_n, uint64_t *psi) {
   if (!psi || log_n < 1 || log_n > 30) return HENTT_EINVAL;
