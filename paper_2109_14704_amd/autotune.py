@@ -3,12 +3,15 @@
 Candidates are timed only after they reproduce the reference candidate's
 output words exactly (parity gate).  Tuned knob: the number of persistent
 workgroups of an uneven-batch plan.  The cache is keyed by device
-architecture and a signature of the plan (units, tiles, direction).
+architecture, a digest of the kernel sources (a tuned choice is void once
+the kernels change) and a signature of the plan (units, tiles).
 """
 import json
 import os
 
 import torch
+
+from .roofline import source_digest
 
 _CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
 
@@ -51,7 +54,7 @@ def persistent_grid(plan, candidates=None, data=None):
     """Best workgroup count for `plan` (cached).  `data`: optional list of the
     plan's device tensors, used for the parity gate (restored between runs)."""
     info = plan.info()
-    key = "%s/units%d/tiles%d" % (_arch(), info["units"], info["tiles"])
+    key = "%s/%s/units%d/tiles%d" % (_arch(), source_digest(), info["units"], info["tiles"])
     cache = _load()
     if key in cache:
         return int(cache[key])

@@ -106,15 +106,19 @@ __global__ __launch_bounds__(BATCH_LANES) void k_batch(const BatchUnit *__restri
                                                        uint32_t spin_limit) {
   __shared__ uint64_t lds[LdsSize<BATCH_B>::value];
   __shared__ uint32_t s_tile, s_ok;
-  const uint32_t tid = threadIdx.x;
   const uint32_t q = qmap[xcc_id()];
   if (q >= BATCH_NQ) return;  // an XCD the plan did not see: its queue is served elsewhere
   const uint32_t q0 = qoff[q], qn = qoff[q + 1] - q0;
   uint32_t *cnt = ctl + BATCH_NQ + 1;
   for (;;) {
-    if (tid == 0) s_tile = atomicAdd(&ctl[q], 1u);
+    if (threadIdx.x == 0) s_tile = atomicAdd(&ctl[q], 1u);
     __syncthreads();
     const uint32_t ti = s_tile;
+    // The lane index is re-read every tile (opaque to the optimiser), so the
+    // per-lane addressing of every tile path is not hoisted out of this loop
+    // and held live across all of them.
+    uint32_t tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
     if (ti >= qn) return;                           // uniform: every workgroup leaves here
     const BatchTile tile = tiles[q0 + ti];
     const BatchUnit u = units[tile.unit];

@@ -765,7 +765,12 @@ uint32_t pass2_tiles(uint32_t ln, int dir) {
 
 // Places the plan's workgroups (probe kernel), maps XCDs to queues, spreads
 // the units over the queues (largest first, least-loaded queue) and orders
-// each queue: pass 1 of the next D units runs ahead of pass 2.
+// each queue.  A queue is two streams merged: pass-1 (and whole) tiles in
+// unit order, and pass-2 tiles in unit order.  A pass-2 tile is placed at
+// least LOOK tiles after the last pass-1 tile of its unit, where LOOK is
+// twice the number of workgroups serving the queue: by the time a workgroup
+// takes the pass-2 tile, the workgroups that took those pass-1 tiles have
+// most likely finished them, so the dependency wait is rarely taken.
 int plan_queues(hentt_batch_plan *p) {
   const uint32_t grid = std::max(1u, p->grid);
   uint32_t *d_probe = nullptr;
@@ -782,6 +787,9 @@ int plan_queues(hentt_batch_plan *p) {
   for (uint32_t x : where)
     if (qmap[x & 15] == ~0u && nq < BATCH_NQ) qmap[x & 15] = nq++;
   p->nq = nq;
+  std::vector<uint32_t> served(BATCH_NQ, 0);  // workgroups serving each queue
+  for (uint32_t x : where)
+    if (qmap[x & 15] < BATCH_NQ) ++served[qmap[x & 15]];
   // cost of a unit ~ N log N
   std::vector<uint32_t> order(p->units.size());
   for (uint32_t i = 0; i < order.size(); ++i) order[i] = i;
@@ -797,25 +805,33 @@ int plan_queues(hentt_batch_plan *p) {
   }
   std::vector<BatchTile> tiles;
   std::vector<uint32_t> qoff(BATCH_NQ + 1, 0);
-  const uint32_t D = 4;
+  std::vector<size_t> ready(p->units.size(), 0);  // queue position after a unit's last pass-1 tile
   for (uint32_t k = 0; k < BATCH_NQ; ++k) {
     qoff[k] = (uint32_t)tiles.size();
     if (k >= nq) continue;
+    const size_t look = 2 * (size_t)served[k];
     const std::vector<uint32_t> &us = qunits[k];
-    auto emit1 = [&](uint32_t i) {
+    std::vector<BatchTile> first;  // whole and pass-1 tiles, unit order
+    for (uint32_t i : us) {
       const BatchUnit &u = p->units[i];
-      if (u.logn == BATCH_B) tiles.push_back({i, (uint32_t)BT_WHOLE << 16});
-      for (uint32_t t = 0; t < u.pass1; ++t) tiles.push_back({i, ((uint32_t)BT_PASS1 << 16) | t});
-    };
-    auto emit2 = [&](uint32_t i) {
-      const BatchUnit &u = p->units[i];
-      for (uint32_t t = 0; t < pass2_tiles(u.logn, p->dir); ++t) tiles.push_back({i, ((uint32_t)BT_PASS2 << 16) | t});
-    };
-    for (uint32_t j = 0; j < us.size() && j < D; ++j) emit1(us[j]);
-    for (uint32_t j = 0; j < us.size(); ++j) {
-      emit2(us[j]);
-      if (j + D < us.size()) emit1(us[j + D]);
+      if (u.logn == BATCH_B) first.push_back({i, (uint32_t)BT_WHOLE << 16});
+      for (uint32_t t = 0; t < u.pass1; ++t) first.push_back({i, ((uint32_t)BT_PASS1 << 16) | t});
     }
+    size_t next = 0;
+    auto emit_first = [&]() {
+      const BatchTile bt = first[next++];
+      tiles.push_back(bt);
+      if ((bt.kind_idx >> 16) == BT_PASS1 && (bt.kind_idx & 0xffffu) + 1 == p->units[bt.unit].pass1)
+        ready[bt.unit] = tiles.size();
+    };
+    for (uint32_t i : us) {
+      const uint32_t n2 = pass2_tiles(p->units[i].logn, p->dir);
+      if (n2 == 0) continue;
+      // every pass-1 tile of unit i is queued, and LOOK more tiles after it
+      while (next < first.size() && (ready[i] == 0 || tiles.size() < ready[i] + look)) emit_first();
+      for (uint32_t t = 0; t < n2; ++t) tiles.push_back({i, ((uint32_t)BT_PASS2 << 16) | t});
+    }
+    while (next < first.size()) emit_first();
   }
   qoff[BATCH_NQ] = (uint32_t)tiles.size();
   p->ntiles = (uint32_t)tiles.size();

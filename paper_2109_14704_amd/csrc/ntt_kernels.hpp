@@ -63,6 +63,14 @@ struct RoundMap {
   static constexpr uint32_t slot_part(int s) { return g_part(s >> R) | (uint32_t)((s & ((1 << R) - 1)) << LO); }
 };
 
+// Twiddle tables are never written while a kernel runs, so they are read
+// through the constant address space: a wave-uniform index becomes a scalar
+// load even when the table pointer was itself read from memory.
+__device__ __forceinline__ Tw ld_tw(const Tw* t, uint32_t i) {
+  const __attribute__((address_space(4))) uint64_t* p = (const __attribute__((address_space(4))) uint64_t*)(t + i);
+  return Tw{p[0], p[1]};
+}
+
 // ---------------------------------------------------------------- rounds --
 // Forward stages with global index s = LOGN - LO - R + u, u < R.  Stage s
 // pairs j with j + N/2^(s+1) and uses psi_rev[2^s + (j >> (LOGN - s))].
@@ -81,7 +89,7 @@ __device__ __forceinline__ void fwd_round(uint64_t (&x)[1 << E], uint32_t logn, 
 #pragma unroll
       for (int k = 0; k < (1 << R); ++k) {
         if (k & h) continue;
-        const Tw w = tw[base + (k >> (R - u))];
+        const Tw w = ld_tw(tw, base + (k >> (R - u)));
         ct_bfly(x[(g << R) + k], x[(g << R) + k + h], w.w, w.ws, m);
       }
     }
@@ -119,7 +127,7 @@ __device__ __forceinline__ void inv_round(uint64_t (&x)[1 << E], uint32_t logn, 
 #pragma unroll
         for (int k = 0; k < (1 << R); ++k) {
           if (k & d) continue;
-          const Tw w = itw[base + (k >> (u + 1))];
+          const Tw w = ld_tw(itw, base + (k >> (u + 1)));
           gs_bfly(x[(g << R) + k], x[(g << R) + k + d], w.w, w.ws, c.m);
         }
       }
@@ -128,17 +136,31 @@ __device__ __forceinline__ void inv_round(uint64_t (&x)[1 << E], uint32_t logn, 
 }
 
 // ------------------------------------------------------------ data moves --
+// Polynomial words are addressed as a base pointer plus a 32-bit byte offset
+// (every index below lies inside one polynomial or block, < 2^17 words), in
+// the global address space.  The compiler then issues global loads with one
+// base for the wave and one 32-bit offset per lane, instead of a flat load
+// with a 64-bit address per element, which matters where the base pointer
+// was itself read from memory (the persistent batch kernel).
+#define HENTT_GLOBAL __attribute__((address_space(1)))
+__device__ __forceinline__ uint64_t gload(const uint64_t* base, uint32_t i) {
+  return *(const HENTT_GLOBAL uint64_t*)((const HENTT_GLOBAL char*)base + (i << 3));
+}
+__device__ __forceinline__ void gstore(uint64_t* base, uint32_t i, uint64_t v) {
+  *(HENTT_GLOBAL uint64_t*)((HENTT_GLOBAL char*)base + (i << 3)) = v;
+}
+
 template <int B, int E, int LO, int R>
 __device__ __forceinline__ void load_global(uint64_t (&x)[1 << E], const uint64_t* __restrict__ src, uint32_t lp) {
   using M = RoundMap<B, E, LO, R>;
 #pragma unroll
-  for (int s = 0; s < (1 << E); ++s) x[s] = src[lp + M::slot_part(s)];
+  for (int s = 0; s < (1 << E); ++s) x[s] = gload(src, lp + M::slot_part(s));
 }
 template <int B, int E, int LO, int R>
 __device__ __forceinline__ void store_global(const uint64_t (&x)[1 << E], uint64_t* __restrict__ dst, uint32_t lp) {
   using M = RoundMap<B, E, LO, R>;
 #pragma unroll
-  for (int s = 0; s < (1 << E); ++s) dst[lp + M::slot_part(s)] = x[s];
+  for (int s = 0; s < (1 << E); ++s) gstore(dst, lp + M::slot_part(s), x[s]);
 }
 template <int B, int E, int LO, int R>
 __device__ __forceinline__ void load_lds(uint64_t (&x)[1 << E], const uint64_t* lds, uint32_t lp) {
