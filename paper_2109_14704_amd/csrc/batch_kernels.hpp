@@ -98,6 +98,13 @@ enum { BATCH_NQ = 8 };
 
 __device__ __forceinline__ uint32_t xcc_id() { return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 15u; }
 
+// Invalidates this CU's vector L1 (the workgroup-scope invalidate of the
+// CDNA3/4 memory model), so the loads that follow read pass-1 results from
+// the XCD's L2.  An agent-scope acquire fence would also invalidate the L2's
+// non-coherent lines; it is not needed (both passes of a unit run on one
+// XCD) and it made pass-2 tiles about 1.6x slower.
+__device__ __forceinline__ void invalidate_l1() { asm volatile("buffer_inv sc0" ::: "memory"); }
+
 template <bool INV>
 __global__ __launch_bounds__(BATCH_LANES) void k_batch(const BatchUnit *__restrict__ units,
                                                        const BatchTile *__restrict__ tiles,
@@ -138,7 +145,7 @@ __global__ __launch_bounds__(BATCH_LANES) void k_batch(const BatchUnit *__restri
         s_ok = ok;
       }
       __syncthreads();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // drop stale L1 lines before reading pass-1 results
+      invalidate_l1();  // drop stale L1 lines before reading pass-1 results
       if (!s_ok) {
         __syncthreads();
         continue;
