@@ -303,6 +303,24 @@ struct ColArgs {
   uint64_t src_sb, dst_sb;  // words between consecutive batch entries
 };
 
+// One column of the column pass: 2^E elements at stride N / 2^E starting at
+// word `col`, read from src and written to dst (equal for in place).  `t` is
+// the limb's forward table, or its inverse table when INV.
+template <int LOGN, int E, bool INV>
+__device__ __forceinline__ void col_pass(const uint64_t *src, uint64_t *dst, uint32_t col, const Tw *t,
+                                         const LimbConst &c) {
+  constexpr int LO = LOGN - E;
+  uint64_t v[1 << E];
+  load_global<LOGN, E, LO, E>(v, src, col);
+  if constexpr (!INV) {
+    fwd_round<LOGN, E, LO, E>(v, LOGN, 0, col, t, c.m);
+  } else {
+    inv_round<LOGN, E, LO, E>(v, LOGN, 0, col, t, c);
+    reduce_inv<E>(v, c.m);
+  }
+  store_global<LOGN, E, LO, E>(v, dst, col);
+}
+
 template <int LOGN, int E, bool INV>
 __global__ __launch_bounds__(256) void k_cols(ColArgs a, const Tw *__restrict__ tw, const LimbConst *__restrict__ lc,
                                               uint32_t batch, uint32_t limbs) {
@@ -316,19 +334,7 @@ __global__ __launch_bounds__(256) void k_cols(ColArgs a, const Tw *__restrict__ 
   const uint64_t off = (uint64_t)limb << LOGN;
   const uint64_t *src = a.src[comp] + (uint64_t)b * a.src_sb + off;
   uint64_t *dst = a.dst[comp] + (uint64_t)b * a.dst_sb + off;
-  const uint32_t col = tile * 256 + threadIdx.x;
-  constexpr int LO = LOGN - E;
-  uint64_t v[1 << E];
-  load_global<LOGN, E, LO, E>(v, src, col);
-  if constexpr (!INV) {
-    const Tw *t = tw + (size_t)limb * 2 * (1u << LOGN);
-    fwd_round<LOGN, E, LO, E>(v, LOGN, 0, col, t, c.m);
-  } else {
-    const Tw *it = tw + ((size_t)limb * 2 + 1) * (1u << LOGN);
-    inv_round<LOGN, E, LO, E>(v, LOGN, 0, col, it, c);
-    reduce_inv<E>(v, c.m);
-  }
-  store_global<LOGN, E, LO, E>(v, dst, col);
+  col_pass<LOGN, E, INV>(src, dst, tile * 256 + threadIdx.x, tw + ((size_t)limb * 2 + (INV ? 1 : 0)) * (1u << LOGN), c);
 }
 
 // Block pass of the forward transform: stages LOGN-B .. LOGN-1 on contiguous

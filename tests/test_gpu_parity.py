@@ -93,6 +93,28 @@ def test_ct_tensor_flags(gpu, log_n, in_ntt, out_ntt):
     assert np.array_equal(host(cd), cin) and np.array_equal(host(dd), din)   # inputs untouched
 
 
+@pytest.mark.parametrize("log_n", [13, 14, 15, 16, 17])
+@pytest.mark.parametrize("batch,limbs", [(1, 1), (3, 2), (13, 5)])
+def test_fused_product_shapes(gpu, log_n, batch, limbs):
+    """Fused polymul and tensor for every size of the two-pass split and unit
+    counts from 1 to 65, compared element by element."""
+    import paper_2109_14704_amd as H
+    print("case fused products log_n=%d batch=%d limbs=%d" % (log_n, batch, limbs), flush=True)
+    rng = np.random.default_rng(300 + 7 * log_n + batch * limbs)
+    mods = CHAIN[:limbs]
+    t = H.Tables(log_n, mods)
+    a = rand_limbs(rng, (batch, limbs, 1 << log_n), mods)
+    b = rand_limbs(rng, (batch, limbs, 1 << log_n), mods)
+    got = H.polymul(t, dev(a, gpu), dev(b, gpu))
+    assert np.array_equal(host(got), oracle.batch_polymul(a, b, mods))
+    if log_n <= 16:
+        c = rand_limbs(rng, (batch, 2, limbs, 1 << log_n), mods)
+        d = rand_limbs(rng, (batch, 2, limbs, 1 << log_n), mods)
+        want = oracle.batch_ntt(oracle.batch_tensor(oracle.batch_ntt(c, mods, +1), oracle.batch_ntt(d, mods, +1), mods),
+                                mods, -1)
+        assert np.array_equal(host(H.ct_tensor(t, dev(c, gpu), dev(d, gpu))), want)
+
+
 def test_plain4096_workload(gpu):
     """Workload 1 at full size: 8 polys fwd + inv, one polymul vs schoolbook."""
     import paper_2109_14704_amd as H
