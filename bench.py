@@ -27,8 +27,9 @@ METRIC = "NTT Gcoeff/s & % HBM/int-mul roofline, batched vs per-poly; p50/p99 ct
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=20,
+                    help="untimed steps; the clocks settle after about 20 steps of the default workload")
     ap.add_argument("--workload", default="ckks_level",
                     choices=["ckks_level", "ct_tensor", "plain4096", "uneven", "serving"])
     ap.add_argument("--requests", type=int, default=2200, help="serving: requests per trace (first 200 warm up)")

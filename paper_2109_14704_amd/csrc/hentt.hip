@@ -790,18 +790,54 @@ int plan_queues(hentt_batch_plan *p) {
   std::vector<uint32_t> served(BATCH_NQ, 0);  // workgroups serving each queue
   for (uint32_t x : where)
     if (qmap[x & 15] < BATCH_NQ) ++served[qmap[x & 15]];
-  // cost of a unit ~ N log N
-  std::vector<uint32_t> order(p->units.size());
-  for (uint32_t i = 0; i < order.size(); ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return p->units[a].logn > p->units[b].logn; });
-  std::vector<std::vector<uint32_t>> qunits(nq);
+  // Units that share a twiddle table (same limb, size and direction) go to
+  // one queue back to back, so that the table is read into that XCD's L2 once
+  // rather than from memory per unit: the block pass of an N = 2^17
+  // transform reads about as many twiddle bytes as data bytes.  Groups are cut
+  // into pieces of at most half a fair share (cost ~ N log N per unit) and the
+  // pieces placed largest first on the least-loaded queue; each queue then
+  // runs its pieces largest N first.
+  auto cost = [&](uint32_t i) { return (double)(1u << p->units[i].logn) * p->units[i].logn; };
+  std::map<const Tw *, std::vector<uint32_t>> by_table;
+  double total = 0;
+  for (uint32_t i = 0; i < p->units.size(); ++i) {
+    by_table[p->units[i].tw].push_back(i);
+    total += cost(i);
+  }
+  const double cap = std::max(total / nq / 2, 1.0);
+  std::vector<std::vector<uint32_t>> pieces;
+  for (auto &g : by_table) {
+    std::vector<uint32_t> cur;
+    double c = 0;
+    for (uint32_t i : g.second) {
+      if (!cur.empty() && c + cost(i) > cap) {
+        pieces.push_back(cur);
+        cur.clear();
+        c = 0;
+      }
+      cur.push_back(i);
+      c += cost(i);
+    }
+    if (!cur.empty()) pieces.push_back(cur);
+  }
+  auto piece_cost = [&](const std::vector<uint32_t> &pc) { return cost(pc[0]) * pc.size(); };
+  std::stable_sort(pieces.begin(), pieces.end(),
+                   [&](const std::vector<uint32_t> &a, const std::vector<uint32_t> &b) { return piece_cost(a) > piece_cost(b); });
+  std::vector<std::vector<const std::vector<uint32_t> *>> qpieces(nq);
   std::vector<double> load(nq, 0.0);
-  for (uint32_t i : order) {
+  for (const auto &pc : pieces) {
     uint32_t best = 0;
     for (uint32_t k = 1; k < nq; ++k)
       if (load[k] < load[best]) best = k;
-    qunits[best].push_back(i);
-    load[best] += (double)(1u << p->units[i].logn) * p->units[i].logn;
+    qpieces[best].push_back(&pc);
+    load[best] += piece_cost(pc);
+  }
+  std::vector<std::vector<uint32_t>> qunits(nq);
+  for (uint32_t k = 0; k < nq; ++k) {
+    std::stable_sort(qpieces[k].begin(), qpieces[k].end(), [&](const std::vector<uint32_t> *a, const std::vector<uint32_t> *b) {
+      return p->units[(*a)[0]].logn > p->units[(*b)[0]].logn;
+    });
+    for (const auto *pc : qpieces[k]) qunits[k].insert(qunits[k].end(), pc->begin(), pc->end());
   }
   std::vector<BatchTile> tiles;
   std::vector<uint32_t> qoff(BATCH_NQ + 1, 0);
