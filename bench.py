@@ -31,7 +31,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20,
                     help="untimed steps; the clocks settle after about 20 steps of the default workload")
     ap.add_argument("--workload", default="ckks_level",
-                    choices=["ckks_level", "ct_tensor", "plain4096", "uneven", "serving"])
+                    choices=["ckks_level", "ct_tensor", "plain4096", "uneven", "serving", "ladder"])
     ap.add_argument("--requests", type=int, default=2200, help="serving: requests per trace (first 200 warm up)")
     ap.add_argument("--grid", type=int, default=0, help="persistent workgroups for the uneven batch (0 = tuned/default)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -242,6 +242,8 @@ def kernel_work(name, info):
         return 8.0 * (n_in + n_out) * L * n, bfly(n_in + n_out, stages) + prod_mul
     if base in ("k_fwd_whole", "k_inv_whole"):
         return 16.0 * n_in * L * n, bfly(n_in, logn)
+    if base in ("k_fwd_blocks", "k_inv_blocks"):
+        return 16.0 * n_in * L * n, bfly(n_in, logn - t_cols)
     return None, None
 
 
@@ -278,6 +280,67 @@ def roofline(prof, info, steps):
               "unit": "T VALU-op/s", "frac": round(ach / R.VALU_PEAK_TOPS, 4)}
     rl.update({"kernel": name, "launch_ms": round(per_launch_s * 1e3, 4), "traffic": R.stored_traffic(name)})
     return rl, name, per_launch_s
+
+
+def bench_ladder(args):
+    """The kernel-design ladder of the paper's NTT evaluation on its own shape:
+    forward transforms of [1024][8][2^15] (8 primes of 55 bits) by the naive
+    radix-2 design, staged designs with radix-4/8/16 LDS rounds, and the
+    library's kernels.  Each design's time, speedup over naive, and VALU
+    roofline fraction (21 ops per butterfly)."""
+    import torch
+    import workloads
+    import paper_2109_14704_amd as H
+    polys, L, logn = 1024, 8, 15
+    n = 1 << logn
+    mods = workloads.moduli("ct_tensor")[:L]
+    t = H.Tables(logn, mods)
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(2109_14704 + 6)
+    x = torch.empty((polys, L, n), dtype=torch.int64, device="cuda:0")
+    for l, q in enumerate(mods):                  # uniform [0, q) per limb, on the device
+        x[:, l].copy_(torch.randint(0, q, (polys, n), generator=gen, device="cuda:0", dtype=torch.int64))
+    coeffs = polys * L * n
+    ops = 21.0 * polys * L * (n // 2) * logn
+    from paper_2109_14704_amd import roofline as R
+    designs = [(H.VARIANT_NAIVE, "naive radix-2, one global-memory launch per stage"),
+               (H.VARIANT_STAGED_R4, "column pass + LDS blocks of 4096, radix-4 rounds"),
+               (H.VARIANT_STAGED_R8, "column pass + LDS blocks of 4096, radix-8 rounds (the paper's best)"),
+               (H.VARIANT_STAGED_R16, "column pass + LDS blocks of 4096, radix-16 rounds"),
+               (H.VARIANT_LIBRARY, "library: 5-stage radix-32 column pass + radix-16 LDS blocks of 1024")]
+    rows = []
+    for v, desc in designs:
+        for _ in range(max(2, args.warmup // 4)):
+            H.ntt_fwd_variant(t, x, v)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        k = max(3, args.steps // 3)
+        a.record()
+        for _ in range(k):
+            H.ntt_fwd_variant(t, x, v)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / k
+        rows.append({"variant": v, "design": desc, "ms": round(ms, 4), "gcoeff_s": round(coeffs / ms / 1e6, 3),
+                     "alu_frac": round(ops / (ms / 1e3) / (R.VALU_PEAK_TOPS * 1e12), 4)})
+    base = rows[0]["ms"]
+    for r in rows:
+        r["x_naive"] = round(base / r["ms"], 2)
+    lib_row = rows[-1]
+    H.prof_enable(True)
+    for _ in range(3):
+        H.ntt_fwd(t, x)
+    torch.cuda.synchronize()
+    prof = H.prof_read()
+    H.prof_enable(False)
+    info = {"workload": "ladder", "N": n, "limbs": L, "polys": polys, "ops": "fwd (the paper's NTT shape)"}
+    rl, _, _ = roofline(prof, info, 3)
+    result = {"metric": METRIC, "value": lib_row["gcoeff_s"], "unit": "Gcoeff/s", "n_gpus": 1,
+              "steps": max(3, args.steps // 3), "warmup": max(2, args.warmup // 4), "ms_per_step": lib_row["ms"],
+              "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+              "data": "synthetic", "config": info, "roofline": rl,
+              "kernels_ms": {kk: round(vv[0] / vv[1], 4) for kk, vv in sorted(prof.items())}, "ladder": rows}
+    print(json.dumps(result), flush=True)
 
 
 def bench_serving(args):
@@ -348,6 +411,11 @@ def bench_serving(args):
 
 def main():
     args = parse()
+    if args.workload == "ladder":
+        if args.gpus != 1:
+            print("bench.py: one GPU only", file=sys.stderr)
+            sys.exit(2)
+        return bench_ladder(args)
     if args.workload == "serving":
         if args.gpus != 1:
             print("bench.py: one GPU only", file=sys.stderr)

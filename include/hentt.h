@@ -79,9 +79,12 @@ int hentt_tables_view(const hentt_tables *t, uint32_t limbs, hentt_tables **view
 /* log_n and limb count of a handle. */
 int hentt_tables_info(const hentt_tables *t, uint32_t *log_n, uint32_t *limbs);
 
-/* Device pointers of the raw tables: fwd and inv are [limbs][N] arrays of
- * (W, W') uint64 pairs (W = psi^brv(k), resp. psi^-brv(k)); moduli is
- * [limbs] of 8-word records whose first word is q.  Read-only. */
+/* Device pointers of the raw tables, read-only.  The twiddles form one
+ * [limbs][2][N] array of (W, W') uint64 pairs, W' = floor(W 2^64 / q): fwd
+ * points at limb 0's forward table (W = psi^brv(k)) and inv at limb 0's
+ * inverse table (W = psi^-brv(k)); limb l's tables start 4 N l words later.
+ * moduli points at [limbs] records of 12 uint64 words whose first word is q
+ * (the rest are the library's reduction constants). */
 int hentt_tables_device_ptrs(const hentt_tables *t, const uint64_t **fwd, const uint64_t **inv,
                              const uint64_t **moduli);
 
@@ -92,6 +95,27 @@ int hentt_psi(uint64_t q, uint32_t log_n, uint64_t *psi);
 /* Forward negacyclic NTT in place: x[batch][limbs][N], natural order ->
  * bit-reversed NTT domain (section II-B). */
 int hentt_ntt_fwd(const hentt_tables *t, uint64_t *x, uint32_t batch, void *stream);
+
+/* Kernel-design ladder of the forward transform (section III-B and the
+ * NTT evaluation of section IV): the same result as hentt_ntt_fwd, computed
+ * by reference kernel designs so that they can be timed against each other.
+ * Not for production use.
+ *   HENTT_VARIANT_LIBRARY    the library's kernels (hentt_ntt_fwd);
+ *   HENTT_VARIANT_NAIVE      naive radix-2: one global-memory launch per
+ *                            stage, one butterfly per lane, then a separate
+ *                            reduction to [0, q); any supported log_n;
+ *   HENTT_VARIANT_STAGED_R4, _R8, _R16
+ *                            one radix-8 column pass, then LDS blocks of 4096
+ *                            coefficients with radix-4, -8 or -16 rounds;
+ *                            log_n = 15 only (HENTT_EINVAL otherwise).
+ * Arguments, layout and errors as hentt_ntt_fwd; HENTT_EINVAL for an unknown
+ * variant. */
+#define HENTT_VARIANT_LIBRARY 0
+#define HENTT_VARIANT_NAIVE 1
+#define HENTT_VARIANT_STAGED_R4 2
+#define HENTT_VARIANT_STAGED_R8 3
+#define HENTT_VARIANT_STAGED_R16 4
+int hentt_ntt_fwd_variant(const hentt_tables *t, uint64_t *x, uint32_t batch, int variant, void *stream);
 
 /* Inverse negacyclic NTT in place: bit-reversed NTT domain -> natural order,
  * including N^-1 and the psi^-i untwist (section II-B). */

@@ -12,7 +12,7 @@ import os
 import torch
 
 __all__ = ["HenttError", "Tables", "ntt_fwd", "ntt_inv", "dyadic_mul", "polymul", "ct_tensor", "ntt_batch",
-           "psi", "lib", "LIB_PATH", "prof_enable", "prof_read", "BatchPlan", "stage_split"]
+           "psi", "lib", "LIB_PATH", "prof_enable", "prof_read", "BatchPlan", "stage_split", "ntt_fwd_variant"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("HENTT_LIB") or os.path.join(_HERE, "libhentt.so")  # HENTT_LIB: alternative build
@@ -50,6 +50,7 @@ def lib():
             "hentt_tables_device_ptrs": [_VP, ctypes.POINTER(_VP), ctypes.POINTER(_VP), ctypes.POINTER(_VP)],
             "hentt_psi": [_U64, _U32, ctypes.POINTER(_U64)],
             "hentt_ntt_fwd": [_VP, _VP, _U32, _VP],
+            "hentt_ntt_fwd_variant": [_VP, _VP, _U32, ctypes.c_int, _VP],
             "hentt_ntt_inv": [_VP, _VP, _U32, _VP],
             "hentt_dyadic_mul": [_VP, _VP, _VP, _VP, _U32, _VP],
             "hentt_polymul": [_VP, _VP, _VP, _VP, _U32, _VP],
@@ -200,6 +201,18 @@ def ntt_fwd(tables, x, stream=None):
     """In-place forward negacyclic NTT of x[..., limbs, N] (bit-reversed output)."""
     _check(lib().hentt_ntt_fwd(tables.handle, _words(x, "x"), _batch_of(tables, x), _stream(stream)),
            "hentt_ntt_fwd")
+    return x
+
+
+# Kernel designs of hentt_ntt_fwd_variant (the ladder of section III-B).
+VARIANT_LIBRARY, VARIANT_NAIVE, VARIANT_STAGED_R4, VARIANT_STAGED_R8, VARIANT_STAGED_R16 = 0, 1, 2, 3, 4
+
+
+def ntt_fwd_variant(tables, x, variant, stream=None):
+    """Forward NTT of x[..., limbs, N] in place by one of the reference kernel
+    designs (VARIANT_*); same result as ntt_fwd."""
+    _check(lib().hentt_ntt_fwd_variant(tables.handle, _words(x, "x"), _batch_of(tables, x), int(variant),
+                                       _stream(stream)), "hentt_ntt_fwd_variant")
     return x
 
 

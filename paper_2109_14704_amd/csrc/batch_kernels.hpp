@@ -37,10 +37,10 @@ __device__ __forceinline__ void batch_fwd_block(uint64_t *p, uint32_t blockStart
                                                 const ModQ &m, uint64_t *lds, uint32_t tid) {
   using F = FwdFirst<BATCH_B, BATCH_E>;
   uint64_t v[1 << BATCH_E];
-  load_global<BATCH_B, BATCH_E, F::LO, F::R, false>(v, p, RoundMap<BATCH_B, BATCH_E, F::LO, F::R>::lane_part(tid));
+  load_global<BATCH_B, BATCH_E, F::LO, F::R>(v, p, RoundMap<BATCH_B, BATCH_E, F::LO, F::R>::lane_part(tid));
   fwd_block_rounds<BATCH_B, BATCH_E, F::LO, F::R>(v, logn, lds, tid, blockStart, t, m);
   reduce_fwd<BATCH_E>(v, m);
-  store_global<BATCH_B, BATCH_E, 0, BATCH_E, false>(v, p, RoundMap<BATCH_B, BATCH_E, 0, BATCH_E>::lane_part(tid));
+  store_global<BATCH_B, BATCH_E, 0, BATCH_E>(v, p, RoundMap<BATCH_B, BATCH_E, 0, BATCH_E>::lane_part(tid));
 }
 
 // Inverse block pass (stages 0 .. 11); canonical when it is the whole transform.
@@ -48,10 +48,10 @@ __device__ __forceinline__ void batch_inv_block(uint64_t *p, uint32_t blockStart
                                                 const LimbConst &c, uint64_t *lds, uint32_t tid) {
   using L = InvLast<BATCH_B, BATCH_E>;
   uint64_t v[1 << BATCH_E];
-  load_global<BATCH_B, BATCH_E, 0, BATCH_E, false>(v, p, RoundMap<BATCH_B, BATCH_E, 0, BATCH_E>::lane_part(tid));
+  load_global<BATCH_B, BATCH_E, 0, BATCH_E>(v, p, RoundMap<BATCH_B, BATCH_E, 0, BATCH_E>::lane_part(tid));
   inv_block_rounds<BATCH_B, BATCH_E, 0, BATCH_E>(v, logn, lds, tid, blockStart, it, c);
   if (logn == BATCH_B) reduce_inv<BATCH_E>(v, c.m);
-  store_global<BATCH_B, BATCH_E, L::LO, L::R, false>(v, p, RoundMap<BATCH_B, BATCH_E, L::LO, L::R>::lane_part(tid));
+  store_global<BATCH_B, BATCH_E, L::LO, L::R>(v, p, RoundMap<BATCH_B, BATCH_E, L::LO, L::R>::lane_part(tid));
 }
 
 // Column pass of 2^EC stages (N = 2^(12+EC)) on a tile of 4096 coefficients:
@@ -65,14 +65,14 @@ __device__ __forceinline__ void batch_cols(uint64_t *p, uint32_t tile, uint32_t 
   for (uint32_t j = 0; j < CPL; ++j) {
     const uint32_t col = (tile * CPL + j) * BATCH_LANES + tid;
     uint64_t v[1 << EC];
-    load_global<LOGN, EC, LO, EC, false>(v, p, col);
+    load_global<LOGN, EC, LO, EC>(v, p, col);
     if constexpr (!INV) {
       fwd_round<LOGN, EC, LO, EC>(v, LOGN, 0, col, t, c.m);
     } else {
       inv_round<LOGN, EC, LO, EC>(v, LOGN, 0, col, t, c);
       reduce_inv<EC>(v, c.m);
     }
-    store_global<LOGN, EC, LO, EC, false>(v, p, col);
+    store_global<LOGN, EC, LO, EC>(v, p, col);
   }
 }
 

@@ -478,6 +478,53 @@ int run_transform(const hentt_tables *t, uint64_t *x, uint32_t batch, hipStream_
   return join_streams(d, st);
 }
 
+// Design-ladder variants of the forward transform (section III-B): the naive
+// radix-2 baseline, and staged transforms whose LDS rounds are radix-4, -8 or
+// -16 on blocks of 4096 coefficients (the paper's work-group tile) after one
+// radix-8 column pass.
+template <int E> void launch_staged15(const hentt_tables *t, uint64_t *x, uint32_t batch, hipStream_t st) {
+  const uint32_t L = t->limbs, units = batch * L;
+  const char *name = E == 2 ? "k_fwd_blocks_r4" : E == 3 ? "k_fwd_blocks_r8" : "k_fwd_blocks_r16";
+  { LaunchTimer lt_("k_cols_fwd_r8", 15, st); hipLaunchKernelGGL((k_cols<15, 3, false>), dim3(units * ((1u << 12) / 256)), dim3(256), 0, st, col_args(x, (uint64_t)L << 15), t->s->d_tw, t->s->d_lc, batch, L); }
+  { LaunchTimer lt_(name, 15, st); hipLaunchKernelGGL((k_fwd_blocks<15, 12, E>), dim3(units << 3), dim3(1 << (12 - E)), 0, st, x, t->s->d_tw, t->s->d_lc, batch, L); }
+}
+
+int run_fwd_variant(const hentt_tables *t, uint64_t *x, uint32_t batch, int variant, hipStream_t st) {
+  const uint32_t ln = t->s->log_n, L = t->limbs;
+  const uint64_t units = (uint64_t)batch * L;
+  switch (variant) {
+    case HENTT_VARIANT_LIBRARY:
+      return run_transform(t, x, batch, st, false);
+    case HENTT_VARIANT_NAIVE: {
+      const uint64_t grid = ((units << (ln - 1)) + 255) / 256, words = units << ln;
+      if (grid > 0x7fffffffu || (words + 255) / 256 > 0x7fffffffu) return HENTT_EINVAL;
+      for (uint32_t s = 0; s < ln; ++s) {
+        LaunchTimer lt_("k_naive_stage", (int)ln, st);
+        hipLaunchKernelGGL(k_naive_stage, dim3((uint32_t)grid), dim3(256), 0, st, x, t->s->d_tw, t->s->d_lc,
+                           (uint32_t)units, L, ln, s);
+      }
+      {
+        LaunchTimer lt_("k_reduce8q", (int)ln, st);
+        hipLaunchKernelGGL(k_reduce8q, dim3((uint32_t)((words + 255) / 256)), dim3(256), 0, st, x, t->s->d_lc, words, L,
+                           ln);
+      }
+      break;
+    }
+    case HENTT_VARIANT_STAGED_R4:
+    case HENTT_VARIANT_STAGED_R8:
+    case HENTT_VARIANT_STAGED_R16:
+      if (ln != 15) return HENTT_EINVAL;
+      if (variant == HENTT_VARIANT_STAGED_R4) launch_staged15<2>(t, x, batch, st);
+      else if (variant == HENTT_VARIANT_STAGED_R8) launch_staged15<3>(t, x, batch, st);
+      else launch_staged15<4>(t, x, batch, st);
+      break;
+    default:
+      return HENTT_EINVAL;
+  }
+  HIPCHK(hipGetLastError());
+  return HENTT_OK;
+}
+
 int run_prod(const hentt_tables *t, int mode, const ProdArgs &pa, uint32_t batch, bool in_coeff, bool out_coeff,
              hipStream_t st) {
   const int ln = (int)t->s->log_n;
@@ -669,6 +716,11 @@ int hentt_tables_device_ptrs(const hentt_tables *t, const uint64_t **fwd, const 
 int hentt_ntt_fwd(const hentt_tables *t, uint64_t *x, uint32_t batch, void *stream) {
   if (!t || !x || batch == 0) return HENTT_EINVAL;
   return run_transform(t, x, batch, (hipStream_t)stream, false);
+}
+
+int hentt_ntt_fwd_variant(const hentt_tables *t, uint64_t *x, uint32_t batch, int variant, void *stream) {
+  if (!t || !x || batch == 0) return HENTT_EINVAL;
+  return run_fwd_variant(t, x, batch, variant, (hipStream_t)stream);
 }
 
 int hentt_ntt_inv(const hentt_tables *t, uint64_t *x, uint32_t batch, void *stream) {

@@ -29,6 +29,8 @@ struct LimbConst {
   uint32_t k, pad;
 };
 
+static_assert(sizeof(LimbConst) == 96, "limb records are 12 words (documented in the C ABI)");
+
 struct alignas(16) Tw { uint64_t w, ws; };
 
 // LDS padding: one spare element after every 16, so that the lane-strided
@@ -143,12 +145,14 @@ __device__ __forceinline__ void inv_round(uint64_t (&x)[1 << E], uint32_t logn, 
 // with a 64-bit address per element, which matters where the base pointer
 // was itself read from memory (the persistent batch kernel).
 //
-// NT: non-temporal (streaming) accesses.  Every pass of the separate-launch
-// kernels reads and writes each word once, and the next pass over it comes
-// after the whole batch has streamed through the caches; marking them
-// streaming keeps the twiddle tables cached and made the column passes
-// 10-18% faster.  The persistent batch kernel reads its pass-1 results back
-// from L2 and uses ordinary accesses.
+// NT: non-temporal (streaming) accesses, chosen per kernel by measurement:
+// the column passes stream both ways (each word is read and written once, and
+// the next pass over it comes after the whole batch has gone through the
+// caches: 10-18% faster), the fused product kernels stream their loads (2-4%
+// faster).  The block and whole-transform kernels, and the persistent batch
+// kernel (which reads pass-1 results back from L2), were slower with
+// streaming accesses (the forward block pass at N = 2^15 took twice as long)
+// and use ordinary ones.
 #define HENTT_GLOBAL __attribute__((address_space(1)))
 template <bool NT> __device__ __forceinline__ uint64_t gload(const uint64_t* base, uint32_t i) {
   const HENTT_GLOBAL uint64_t* p = (const HENTT_GLOBAL uint64_t*)((const HENTT_GLOBAL char*)base + (i << 3));
@@ -161,13 +165,13 @@ template <bool NT> __device__ __forceinline__ void gstore(uint64_t* base, uint32
   else *p = v;
 }
 
-template <int B, int E, int LO, int R, bool NT = true>
+template <int B, int E, int LO, int R, bool NT = false>
 __device__ __forceinline__ void load_global(uint64_t (&x)[1 << E], const uint64_t* __restrict__ src, uint32_t lp) {
   using M = RoundMap<B, E, LO, R>;
 #pragma unroll
   for (int s = 0; s < (1 << E); ++s) x[s] = gload<NT>(src, lp + M::slot_part(s));
 }
-template <int B, int E, int LO, int R, bool NT = true>
+template <int B, int E, int LO, int R, bool NT = false>
 __device__ __forceinline__ void store_global(const uint64_t (&x)[1 << E], uint64_t* __restrict__ dst, uint32_t lp) {
   using M = RoundMap<B, E, LO, R>;
 #pragma unroll
@@ -322,14 +326,14 @@ __device__ __forceinline__ void col_pass(const uint64_t *src, uint64_t *dst, uin
                                          const LimbConst &c) {
   constexpr int LO = LOGN - E;
   uint64_t v[1 << E];
-  load_global<LOGN, E, LO, E>(v, src, col);
+  load_global<LOGN, E, LO, E, true>(v, src, col);
   if constexpr (!INV) {
     fwd_round<LOGN, E, LO, E>(v, LOGN, 0, col, t, c.m);
   } else {
     inv_round<LOGN, E, LO, E>(v, LOGN, 0, col, t, c);
     reduce_inv<E>(v, c.m);
   }
-  store_global<LOGN, E, LO, E>(v, dst, col);
+  store_global<LOGN, E, LO, E, true>(v, dst, col);
 }
 
 template <int LOGN, int E, bool INV>
@@ -388,6 +392,42 @@ __global__ __launch_bounds__(1 << (B - E)) void k_inv_blocks(uint64_t *__restric
   load_global<B, E, 0, E>(v, p, RoundMap<B, E, 0, E>::lane_part(tid));
   inv_block_rounds<B, E, 0, E>(v, LOGN, lds, tid, blockStart, it, c);
   store_global<B, E, L::LO, L::R>(v, p, RoundMap<B, E, L::LO, L::R>::lane_part(tid));
+}
+
+// ------------------------------------------------- design-ladder kernels --
+// Reference points for the kernel-design ladder of section III-B, not used by
+// the hot path.  k_naive_stage is the paper's naive radix-2 baseline: one
+// butterfly per lane and one launch per stage, every stage a round trip of
+// the whole batch through global memory (same butterfly arithmetic as the
+// other kernels).  Stage s pairs j with j + N/2^(s+1) and uses
+// psi_rev[2^s + j / (N/2^s)].  k_reduce8q is its separate last-round
+// reduction from [0, 8q) to [0, q).
+__global__ __launch_bounds__(256) void k_naive_stage(uint64_t *__restrict__ x, const Tw *__restrict__ tw,
+                                                     const LimbConst *__restrict__ lc, uint32_t units,
+                                                     uint32_t limbs, uint32_t logn, uint32_t s) {
+  const uint64_t gid = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  const uint32_t lh = logn - 1;
+  const uint64_t unit = gid >> lh;  // (batch entry, limb) polynomial
+  if (unit >= units) return;
+  const uint32_t i = (uint32_t)gid & ((1u << lh) - 1);
+  const uint32_t limb = (uint32_t)(unit % limbs);
+  const ModQ m = lc[limb].m;
+  const uint32_t lt = lh - s;  // log2 of the gap
+  const uint32_t grp = i >> lt;
+  const uint32_t j = (grp << (lt + 1)) | (i & ((1u << lt) - 1));
+  uint64_t *p = x + (unit << logn);
+  const Tw w = tw[((size_t)limb << (logn + 1)) + (1u << s) + grp];
+  uint64_t X = p[j], Y = p[j + (1u << lt)];
+  ct_bfly(X, Y, w.w, w.ws, m);
+  p[j] = X;
+  p[j + (1u << lt)] = Y;
+}
+
+__global__ __launch_bounds__(256) void k_reduce8q(uint64_t *__restrict__ x, const LimbConst *__restrict__ lc,
+                                                  uint64_t words, uint32_t limbs, uint32_t logn) {
+  const uint64_t gid = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (gid >= words) return;
+  x[gid] = reduce_8q(x[gid], lc[(uint32_t)((gid >> logn) % limbs)].m);
 }
 
 // ------------------------------------------------------ fused products ----
@@ -480,11 +520,11 @@ __global__ __launch_bounds__(1 << (B - E)) void k_prod(ProdArgs a, const Tw *__r
       // an opaque copy of the table pointer per input: the twiddles are re-read
       // from cache instead of being hoisted out of the loop into VGPRs
       const Tw *tp = opaque(t);
-      load_global<B, E, F::LO, F::R>(v, a.in[p] + in_off, RoundMap<B, E, F::LO, F::R>::lane_part(tid));
+      load_global<B, E, F::LO, F::R, true>(v, a.in[p] + in_off, RoundMap<B, E, F::LO, F::R>::lane_part(tid));
       fwd_block_rounds<B, E, F::LO, F::R>(v, LOGN, lds, tid, blockStart, tp, c.m);
       reduce_fwd<E>(v, c.m);
     } else {
-      load_global<B, E, 0, E>(v, a.in[p] + in_off, M0::lane_part(tid));
+      load_global<B, E, 0, E, true>(v, a.in[p] + in_off, M0::lane_part(tid));
     }
     static_for<0, NIN>([&](auto P) {
       if (p == decltype(P)::value) {

@@ -115,6 +115,30 @@ def test_fused_product_shapes(gpu, log_n, batch, limbs):
         assert np.array_equal(host(H.ct_tensor(t, dev(c, gpu), dev(d, gpu))), want)
 
 
+@pytest.mark.parametrize("log_n,variant", [(6, 1), (12, 1), (15, 1), (17, 1), (15, 2), (15, 3), (15, 4), (15, 0)])
+def test_design_ladder_variants(gpu, log_n, variant):
+    """Every kernel design of the ladder (naive radix-2, staged radix-4/8/16)
+    gives the forward transform word for word."""
+    import paper_2109_14704_amd as H
+    print("case ladder variant=%d log_n=%d" % (variant, log_n), flush=True)
+    rng = np.random.default_rng(400 + 10 * log_n + variant)
+    mods = CHAIN[:3]
+    x = rand_limbs(rng, (2, 3, 1 << log_n), mods)
+    t = H.Tables(log_n, mods)
+    got = H.ntt_fwd_variant(t, dev(x, gpu), variant)
+    assert np.array_equal(host(got), oracle.batch_ntt(x, mods, +1))
+
+
+def test_design_ladder_rejects(gpu):
+    import paper_2109_14704_amd as H
+    mods = CHAIN[:1]
+    x = dev(rand_limbs(np.random.default_rng(1), (1, 1, 1 << 14), mods), gpu)
+    t = H.Tables(14, mods)
+    for variant in (H.VARIANT_STAGED_R8, 7, -1):
+        with pytest.raises(H.HenttError):
+            H.ntt_fwd_variant(t, x, variant)
+
+
 def test_plain4096_workload(gpu):
     """Workload 1 at full size: 8 polys fwd + inv, one polymul vs schoolbook."""
     import paper_2109_14704_amd as H
