@@ -285,7 +285,7 @@ def roofline(prof, info, steps):
 def bench_ladder(args):
     """The kernel-design ladder of the paper's NTT evaluation on its own shape:
     forward transforms of [1024][8][2^15] (8 primes of 55 bits) by the naive
-    radix-2 design, staged designs with radix-4/8/16 LDS rounds, and the
+    radix-2 design, staged designs with radix-2/4/8/16 LDS rounds, and the
     library's kernels.  Each design's time, speedup over naive, and VALU
     roofline fraction (21 ops per butterfly)."""
     import torch
@@ -304,6 +304,7 @@ def bench_ladder(args):
     ops = 21.0 * polys * L * (n // 2) * logn
     from paper_2109_14704_amd import roofline as R
     designs = [(H.VARIANT_NAIVE, "naive radix-2, one global-memory launch per stage"),
+               (H.VARIANT_STAGED_R2, "4 naive global stages + LDS blocks of 2048, radix-2 rounds"),
                (H.VARIANT_STAGED_R4, "column pass + LDS blocks of 4096, radix-4 rounds"),
                (H.VARIANT_STAGED_R8, "column pass + LDS blocks of 4096, radix-8 rounds (the paper's best)"),
                (H.VARIANT_STAGED_R16, "column pass + LDS blocks of 4096, radix-16 rounds"),

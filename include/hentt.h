@@ -104,6 +104,9 @@ int hentt_ntt_fwd(const hentt_tables *t, uint64_t *x, uint32_t batch, void *stre
  *   HENTT_VARIANT_NAIVE      naive radix-2: one global-memory launch per
  *                            stage, one butterfly per lane, then a separate
  *                            reduction to [0, q); any supported log_n;
+ *   HENTT_VARIANT_STAGED_R2  four naive global stages, then LDS blocks of
+ *                            2048 coefficients with radix-2 rounds (one stage
+ *                            per LDS exchange); log_n = 15 only;
  *   HENTT_VARIANT_STAGED_R4, _R8, _R16
  *                            one radix-8 column pass, then LDS blocks of 4096
  *                            coefficients with radix-4, -8 or -16 rounds;
@@ -115,6 +118,7 @@ int hentt_ntt_fwd(const hentt_tables *t, uint64_t *x, uint32_t batch, void *stre
 #define HENTT_VARIANT_STAGED_R4 2
 #define HENTT_VARIANT_STAGED_R8 3
 #define HENTT_VARIANT_STAGED_R16 4
+#define HENTT_VARIANT_STAGED_R2 5
 int hentt_ntt_fwd_variant(const hentt_tables *t, uint64_t *x, uint32_t batch, int variant, void *stream);
 
 /* Inverse negacyclic NTT in place: bit-reversed NTT domain -> natural order,

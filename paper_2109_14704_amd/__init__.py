@@ -205,7 +205,8 @@ def ntt_fwd(tables, x, stream=None):
 
 
 # Kernel designs of hentt_ntt_fwd_variant (the ladder of section III-B).
-VARIANT_LIBRARY, VARIANT_NAIVE, VARIANT_STAGED_R4, VARIANT_STAGED_R8, VARIANT_STAGED_R16 = 0, 1, 2, 3, 4
+VARIANT_LIBRARY, VARIANT_NAIVE, VARIANT_STAGED_R4, VARIANT_STAGED_R8, VARIANT_STAGED_R16, VARIANT_STAGED_R2 = \
+    0, 1, 2, 3, 4, 5
 
 
 def ntt_fwd_variant(tables, x, variant, stream=None):

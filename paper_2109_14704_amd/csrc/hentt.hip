@@ -479,9 +479,21 @@ int run_transform(const hentt_tables *t, uint64_t *x, uint32_t batch, hipStream_
 }
 
 // Design-ladder variants of the forward transform (section III-B): the naive
-// radix-2 baseline, and staged transforms whose LDS rounds are radix-4, -8 or
-// -16 on blocks of 4096 coefficients (the paper's work-group tile) after one
-// radix-8 column pass.
+// radix-2 baseline; staged radix-2 (four naive global stages, then LDS blocks
+// of 2048 words with radix-2 rounds, one stage per LDS exchange); and staged
+// transforms whose LDS rounds are radix-4, -8 or -16 on blocks of 4096 words
+// (the paper's work-group tile) after one radix-8 column pass.
+void launch_naive_stages(const hentt_tables *t, uint64_t *x, uint64_t units, uint32_t s0, uint32_t s1,
+                         hipStream_t st) {
+  const uint32_t ln = t->s->log_n;
+  const uint64_t grid = ((units << (ln - 1)) + 255) / 256;
+  for (uint32_t s = s0; s < s1; ++s) {
+    LaunchTimer lt_("k_naive_stage", (int)ln, st);
+    hipLaunchKernelGGL(k_naive_stage, dim3((uint32_t)grid), dim3(256), 0, st, x, t->s->d_tw, t->s->d_lc,
+                       (uint32_t)units, t->limbs, ln, s);
+  }
+}
+
 template <int E> void launch_staged15(const hentt_tables *t, uint64_t *x, uint32_t batch, hipStream_t st) {
   const uint32_t L = t->limbs, units = batch * L;
   const char *name = E == 2 ? "k_fwd_blocks_r4" : E == 3 ? "k_fwd_blocks_r8" : "k_fwd_blocks_r16";
@@ -497,12 +509,8 @@ int run_fwd_variant(const hentt_tables *t, uint64_t *x, uint32_t batch, int vari
       return run_transform(t, x, batch, st, false);
     case HENTT_VARIANT_NAIVE: {
       const uint64_t grid = ((units << (ln - 1)) + 255) / 256, words = units << ln;
-      if (grid > 0x7fffffffu || (words + 255) / 256 > 0x7fffffffu) return HENTT_EINVAL;
-      for (uint32_t s = 0; s < ln; ++s) {
-        LaunchTimer lt_("k_naive_stage", (int)ln, st);
-        hipLaunchKernelGGL(k_naive_stage, dim3((uint32_t)grid), dim3(256), 0, st, x, t->s->d_tw, t->s->d_lc,
-                           (uint32_t)units, L, ln, s);
-      }
+      if (grid > 0x7fffffffu || (words + 255) / 256 > 0x7fffffffu || units > 0xffffffffu) return HENTT_EINVAL;
+      launch_naive_stages(t, x, units, 0, ln, st);
       {
         LaunchTimer lt_("k_reduce8q", (int)ln, st);
         hipLaunchKernelGGL(k_reduce8q, dim3((uint32_t)((words + 255) / 256)), dim3(256), 0, st, x, t->s->d_lc, words, L,
@@ -510,6 +518,15 @@ int run_fwd_variant(const hentt_tables *t, uint64_t *x, uint32_t batch, int vari
       }
       break;
     }
+    case HENTT_VARIANT_STAGED_R2:
+      if (ln != 15 || ((units << 14) + 255) / 256 > 0x7fffffffu) return HENTT_EINVAL;
+      launch_naive_stages(t, x, units, 0, 4, st);
+      {
+        LaunchTimer lt_("k_fwd_blocks_r2", 15, st);
+        hipLaunchKernelGGL((k_fwd_blocks<15, 11, 1>), dim3((uint32_t)(units << 4)), dim3(1 << 10), 0, st, x,
+                           t->s->d_tw, t->s->d_lc, batch, L);
+      }
+      break;
     case HENTT_VARIANT_STAGED_R4:
     case HENTT_VARIANT_STAGED_R8:
     case HENTT_VARIANT_STAGED_R16:

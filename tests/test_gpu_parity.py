@@ -115,9 +115,9 @@ def test_fused_product_shapes(gpu, log_n, batch, limbs):
         assert np.array_equal(host(H.ct_tensor(t, dev(c, gpu), dev(d, gpu))), want)
 
 
-@pytest.mark.parametrize("log_n,variant", [(6, 1), (12, 1), (15, 1), (17, 1), (15, 2), (15, 3), (15, 4), (15, 0)])
+@pytest.mark.parametrize("log_n,variant", [(6, 1), (12, 1), (15, 1), (17, 1), (15, 5), (15, 2), (15, 3), (15, 4), (15, 0)])
 def test_design_ladder_variants(gpu, log_n, variant):
-    """Every kernel design of the ladder (naive radix-2, staged radix-4/8/16)
+    """Every kernel design of the ladder (naive radix-2, staged radix-2/4/8/16)
     gives the forward transform word for word."""
     import paper_2109_14704_amd as H
     print("case ladder variant=%d log_n=%d" % (variant, log_n), flush=True)
@@ -134,7 +134,7 @@ def test_design_ladder_rejects(gpu):
     mods = CHAIN[:1]
     x = dev(rand_limbs(np.random.default_rng(1), (1, 1, 1 << 14), mods), gpu)
     t = H.Tables(14, mods)
-    for variant in (H.VARIANT_STAGED_R8, 7, -1):
+    for variant in (H.VARIANT_STAGED_R8, H.VARIANT_STAGED_R2, 7, -1):
         with pytest.raises(H.HenttError):
             H.ntt_fwd_variant(t, x, variant)
 
