@@ -68,6 +68,7 @@ def lib():
             "or_batch_ntt": (ctypes.c_int, [P64, U32, U32, U32, P64, ctypes.c_int, ctypes.c_int]),
             "or_batch_dyadic": (None, [P64, P64, P64, U32, U32, U32, P64]),
             "or_batch_tensor": (None, [P64, P64, P64, U32, U32, U32, P64]),
+            "or_batch_rescale": (None, [P64, P64, U32, U32, U32, P64]),
             "or_batch_polymul": (ctypes.c_int, [P64, P64, P64, U32, U32, U32, P64, ctypes.c_int]),
             "or_batch_ct_tensor_coeff": (ctypes.c_int, [P64, P64, P64, U32, U32, U32, P64, ctypes.c_int]),
         }
@@ -211,6 +212,27 @@ def batch_ct_tensor_coeff(c, d, moduli, threads=0):
     if rc:
         raise ValueError("oracle: bad modulus")
     return out
+
+
+def batch_rescale(x, moduli):
+    """Rescale of section II-A (drop the last prime with rounding), coefficient
+    domain: x [batch][limbs][N] over moduli[:limbs] -> [batch][limbs - 1][N]."""
+    x = _u64(x); m = _moduli(moduli)
+    batch, limbs, n = x.shape
+    if limbs < 2:
+        raise ValueError("oracle: rescale needs at least two limbs")
+    out = np.zeros((batch, limbs - 1, n), dtype=np.uint64)
+    lib().or_batch_rescale(_p(x), _p(out), batch, limbs, n, _p(m[:limbs]))
+    return out
+
+
+def batch_rescale_ntt(c, moduli):
+    """Rescale of NTT-domain ciphertext limbs: the coefficient-domain rescale
+    between an inverse and a forward transform."""
+    c = _u64(c)
+    limbs = c.shape[1]
+    x = batch_ntt(c, moduli[:limbs], -1)
+    return batch_ntt(batch_rescale(x, moduli[:limbs]), moduli[:limbs - 1], +1)
 
 
 def max_threads():

@@ -366,3 +366,28 @@ int or_batch_ct_tensor_coeff(const uint64_t *c, const uint64_t *d, uint64_t *out
   free(tc); free(td);
   return rc;
 }
+
+/* Rescale RS_{l -> l-1} (section II-A): c' = round(c q_{l-1} / q_l) mod q_{l-1}.
+ * In RNS, q_l = q_{l-1} * qL with qL the last prime of the level, so with x the
+ * CRT value of a coefficient's residues x_0 .. x_L (L = limbs - 1):
+ *   out_i = round(x / qL) mod q_i,  i < L.
+ * Steps: qL is odd, so round(x / qL) = floor((x + h) / qL) with h = (qL - 1) / 2;
+ * r = (x_L + h) mod qL is (x + h) mod qL, and x + h - r is divisible by qL:
+ *   out_i = (x_i + h - r) * qL^-1  mod q_i.
+ * x [batch][limbs][N] -> out [batch][limbs - 1][N], coefficient domain. */
+void or_batch_rescale(const uint64_t *x, uint64_t *out, uint32_t batch, uint32_t limbs, uint32_t N,
+                      const uint64_t *moduli) {
+  const uint32_t L = limbs - 1;
+  const uint64_t qL = moduli[L], h = (qL - 1) / 2;
+  for (uint32_t b = 0; b < batch; ++b)
+    for (uint32_t i = 0; i < L; ++i) {
+      const uint64_t q = moduli[i], inv = or_invmod(qL % q, q);
+      const uint64_t *xi = x + ((size_t)b * limbs + i) * N, *xL = x + ((size_t)b * limbs + L) * N;
+      uint64_t *o = out + ((size_t)b * L + i) * N;
+      for (uint32_t k = 0; k < N; ++k) {
+        const uint64_t r = or_addmod(xL[k], h, qL);
+        const uint64_t t = or_submod(or_addmod(xi[k], h % q, q), r % q, q);
+        o[k] = or_mulmod(t, inv, q);
+      }
+    }
+}

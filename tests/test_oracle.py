@@ -267,3 +267,79 @@ def test_twiddle_invariants(log_n):
             assert f[2 * k + 1] == f[2 * k] * f[1] % q
         for k in range(0, n, max(1, n // 512)):
             assert f[k] * i[k] % q == 1
+
+
+# ---------------------------------------------------------------- rescale --
+# RS of section II-A: c' = round(c q_{l-1} / q_l) mod q_{l-1}.  Pinned against
+# the definition itself: CRT reconstruction of each coefficient as a Python
+# integer and exact rational rounding (fractions), independent of the RNS
+# formula the oracle uses.
+def _crt(residues, moduli):
+    Q = 1
+    for q in moduli:
+        Q *= q
+    x = 0
+    for r, q in zip(residues, moduli):
+        Mi = Q // q
+        x += int(r) * Mi * pow(Mi, -1, q)
+    return x % Q, Q
+
+
+def _round_div(x, d):
+    from fractions import Fraction
+    return round(Fraction(x, d))   # d odd: no exact halves, so the tie rule never applies
+
+
+@pytest.mark.parametrize("limbs", [2, 3, 5])
+def test_rescale_is_rounded_division(limbs):
+    import workloads
+    mods = workloads.moduli("ct_tensor")[:limbs]
+    rng = random.Random(70 + limbs)
+    n = 16
+    x = np.array([[[rng.randrange(q) for _ in range(n)] for q in mods] for _ in range(3)], dtype=np.uint64)
+    got = oracle.batch_rescale(x, mods)
+    assert got.shape == (3, limbs - 1, n)
+    for b in range(3):
+        for k in range(n):
+            X, _ = _crt([x[b, l, k] for l in range(limbs)], mods)
+            want = _round_div(X, mods[-1])
+            for i in range(limbs - 1):
+                assert int(got[b, i, k]) == want % mods[i], (b, k, i)
+
+
+def test_rescale_rounding_boundaries():
+    """x = k qL + h rounds down, k qL + h + 1 rounds up (h = (qL - 1) / 2),
+    exact multiples divide exactly, and the largest residue wraps to 0."""
+    import workloads
+    mods = workloads.moduli("ct_tensor")[:3]
+    qL = mods[-1]
+    h = (qL - 1) // 2
+    Q = mods[0] * mods[1] * qL
+    cases = []
+    for k in [0, 1, 12345, mods[0] * mods[1] - 1]:
+        cases += [(k * qL, k), (k * qL + h, k), (k * qL + h + 1, k + 1)]
+    cases = [(x, want) for x, want in cases if x < Q]
+    cases.append((Q - 1, mods[0] * mods[1]))           # rounds up to Q / qL = 0 mod q_i
+    x = np.array([[[X % q for X, _ in cases] for q in mods]], dtype=np.uint64)
+    got = oracle.batch_rescale(x, mods)
+    for k, (X, want) in enumerate(cases):
+        for i in range(2):
+            assert int(got[0, i, k]) == want % mods[i], (X, i)
+
+
+def test_rescale_ntt_domain_is_linear_and_scales_by_the_dropped_prime():
+    """In the NTT domain the rescale commutes with the transforms; for inputs
+    that are exact multiples of qL (x = qL y) it returns NTT(y)."""
+    import workloads
+    mods = workloads.moduli("ct_tensor")[:3]
+    qL = mods[-1]
+    rng = np.random.default_rng(5)
+    n = 64
+    y = np.stack([rng.integers(0, mods[i], size=(2, n), dtype=np.uint64) for i in range(2)], axis=1)
+    # x = qL * y in every limb (residue 0 in the dropped limb)
+    x = np.zeros((2, 3, n), dtype=np.uint64)
+    for i in range(2):
+        x[:, i] = [[(int(v) * qL) % mods[i] for v in row] for row in y[:, i]]
+    X = oracle.batch_ntt(x, mods, +1)
+    got = oracle.batch_rescale_ntt(X, mods)
+    assert np.array_equal(got, oracle.batch_ntt(y, mods[:2], +1))
