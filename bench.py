@@ -31,7 +31,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20,
                     help="untimed steps; the clocks settle after about 20 steps of the default workload")
     ap.add_argument("--workload", default="ckks_level",
-                    choices=["ckks_level", "ct_tensor", "plain4096", "uneven", "serving", "ladder"])
+                    choices=["ckks_level", "ct_tensor", "plain4096", "uneven", "serving", "ladder", "rescale"])
     ap.add_argument("--requests", type=int, default=2200, help="serving: requests per trace (first 200 warm up)")
     ap.add_argument("--grid", type=int, default=0, help="persistent workgroups for the uneven batch (0 = tuned/default)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -127,6 +127,35 @@ def setup(name, torch, H, grid_arg=0):
 
         return dict(step=step, per_poly=per_poly_step, coeffs=2 * coeffs, t=tables, info=info, w={"x": xs},
                     cpu=lambda k: cpu_uneven(jobs, mods, k), plans=(plan_f, plan_i), prof_step=prof_step)
+    if name == "rescale":
+        # RS after Mul at the top of the ct_tensor chain: 32 ciphertexts (64
+        # polynomials) of N = 2^16 at 24 limbs, NTT domain -> 23 limbs
+        mods = workloads.moduli("ct_tensor")
+        polys, L, logn = 64, len(mods), 16
+        n = 1 << logn
+        t = H.Tables(logn, mods)
+        gen = torch.Generator(device="cuda:0")
+        gen.manual_seed(2109_14704 + 7)
+        C = torch.empty((polys, L, n), dtype=torch.int64, device="cuda:0")
+        for l, q in enumerate(mods):
+            C[:, l].copy_(torch.randint(0, q, (polys, n), generator=gen, device="cuda:0", dtype=torch.int64))
+        out = torch.empty((polys, L - 1, n), dtype=torch.int64, device="cuda:0")
+        tmp = torch.empty_like(C)
+        lower = t.view(L - 1)
+
+        def step():
+            H.rescale(t, C, out=out, ntt=True)
+
+        def unfused_step():           # inverse of every limb, coefficient rescale, forward of the rest
+            tmp.copy_(C)
+            H.ntt_inv(t, tmp)
+            H.rescale(t, tmp, out=out)
+            H.ntt_fwd(lower, out)
+
+        info = {"workload": "rescale", "N": n, "limbs": L, "polys": polys,
+                "ops": "RS in the NTT domain: inverse of the last limb, fused forward + subtract + scale per limb"}
+        return dict(step=step, per_poly=unfused_step, coeffs=polys * (L - 1) * n, t=t, info=info,
+                    w={"x": [None] * polys}, cpu=lambda k: cpu_rescale(mods, logn, k))
     w = workloads.plain4096()
     t = H.Tables(12, w["moduli"])
     X = to_dev(w["x"], torch)
@@ -177,6 +206,15 @@ def cpu_uneven(jobs, mods, k):
     return time.perf_counter() - t0, coeffs
 
 
+def cpu_rescale(mods, logn, k):
+    import oracle
+    import workloads
+    x = workloads.uniform(7, 0, (k, len(mods), 1 << logn), mods)
+    t0 = time.perf_counter()
+    oracle.batch_rescale_ntt(x, mods)
+    return time.perf_counter() - t0, k * (len(mods) - 1) << logn
+
+
 def cpu_plain(w, k):
     import oracle
     x = w["x"]
@@ -209,6 +247,7 @@ def cpu_baseline(s, target_s):
 VALU_BFLY = 21     # Harvey/Shoup butterfly: 9 32-bit multiplies + 12 adds, compares, selects
 VALU_PROD = 38     # Barrett product a*b mod q: 128-bit product, quotient estimate, 3 corrections
 VALU_TENSOR = 121  # c0d0, c1d1 (2 x 38) + c0d1 + c1d0 with one reduction (45)
+VALU_RS_EPI = 17   # rescale epilogue: Shoup product by qL^-1 (9 + adds) and a reduction from [0, 4q)
 
 
 def kernel_work(name, info):
@@ -221,6 +260,17 @@ def kernel_work(name, info):
     n, L = info["N"], info["limbs"]
     logn = n.bit_length() - 1
     t_cols, p_cols = H.stage_split(logn)                   # stages in the column passes (library plan)
+    if info["workload"] == "rescale":
+        # per output coefficient: column pass reads the last limb's word and
+        # writes a scratch word; the block pass reads it and c_i and writes the
+        # result; the epilogue is about one Shoup product and a reduction
+        units = info["polys"] * (L - 1)
+        base = name.split("<")[0]
+        if base == "k_rs_cols":
+            return 16.0 * units * n, VALU_BFLY * units * (n // 2) * t_cols
+        if base == "k_rs_blocks":
+            return 24.0 * units * n, VALU_BFLY * units * (n // 2) * (logn - t_cols) + VALU_RS_EPI * units * n
+        return None, None
     if info["workload"] == "ckks_level":
         p = info["polys_per_operand"]
         n_in, n_out, prod_mul = 2 * p, p, VALU_PROD * p * L * n
@@ -475,8 +525,13 @@ def main():
         b.record()
         torch.cuda.synchronize()
         pms = a.elapsed_time(b) / reps
-        result["per_poly"] = {"ms_per_step": round(pms, 4), "value": round(s["coeffs"] / (pms / 1e3) / 1e9, 3),
-                              "unit": "Gcoeff/s", "batched_speedup": round(pms / ms, 3)}
+        if s["info"]["workload"] == "rescale":      # the comparator is the unfused sequence
+            result["unfused"] = {"ms_per_step": round(pms, 4), "value": round(s["coeffs"] / (pms / 1e3) / 1e9, 3),
+                                 "unit": "Gcoeff/s", "fused_speedup": round(pms / ms, 3),
+                                 "ops": "inverse of every limb, coefficient rescale, forward of the rest"}
+        else:
+            result["per_poly"] = {"ms_per_step": round(pms, 4), "value": round(s["coeffs"] / (pms / 1e3) / 1e9, 3),
+                                  "unit": "Gcoeff/s", "batched_speedup": round(pms / ms, 3)}
     if args.calib_copy:
         src = torch.ones(1 << 27, dtype=torch.int64, device="cuda:0")
         dst = torch.empty_like(src)

@@ -96,6 +96,20 @@ int hentt_psi(uint64_t q, uint32_t log_n, uint64_t *psi);
  * bit-reversed NTT domain (section II-B). */
 int hentt_ntt_fwd(const hentt_tables *t, uint64_t *x, uint32_t batch, void *stream);
 
+/* Rescale RS of section II-A: divide by the last prime qL of the level with
+ * rounding and drop that limb, c' = round(c / qL) mod q_i (c the CRT value of
+ * each coefficient).  t's limb count is the level (at least 2); c is
+ * [batch][limbs][N], out [batch][limbs - 1][N]; out must not overlap c
+ * (HENTT_EINVAL).  flags: 0 for coefficient-domain input and output;
+ * HENTT_IN_NTT | HENTT_OUT_NTT for NTT-domain (bit-reversed) input and output,
+ * where the last limb is inverse-transformed once and its correction
+ * forward-transformed per remaining limb, with the reduction, subtraction and
+ * scaling fused into that transform; other flags: HENTT_EINVAL.  Canonical
+ * inputs, canonical outputs.  The per-level constants are made on the first
+ * call for a level (a synchronous upload); later calls only enqueue. */
+int hentt_rescale(const hentt_tables *t, const uint64_t *c, uint64_t *out, uint32_t batch, uint32_t flags,
+                  void *stream);
+
 /* Kernel-design ladder of the forward transform (section III-B and the
  * NTT evaluation of section IV): the same result as hentt_ntt_fwd, computed
  * by reference kernel designs so that they can be timed against each other.

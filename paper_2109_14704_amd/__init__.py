@@ -12,7 +12,8 @@ import os
 import torch
 
 __all__ = ["HenttError", "Tables", "ntt_fwd", "ntt_inv", "dyadic_mul", "polymul", "ct_tensor", "ntt_batch",
-           "psi", "lib", "LIB_PATH", "prof_enable", "prof_read", "BatchPlan", "stage_split", "ntt_fwd_variant"]
+           "psi", "lib", "LIB_PATH", "prof_enable", "prof_read", "BatchPlan", "stage_split", "ntt_fwd_variant",
+           "rescale"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("HENTT_LIB") or os.path.join(_HERE, "libhentt.so")  # HENTT_LIB: alternative build
@@ -51,6 +52,7 @@ def lib():
             "hentt_psi": [_U64, _U32, ctypes.POINTER(_U64)],
             "hentt_ntt_fwd": [_VP, _VP, _U32, _VP],
             "hentt_ntt_fwd_variant": [_VP, _VP, _U32, ctypes.c_int, _VP],
+            "hentt_rescale": [_VP, _VP, _VP, _U32, _U32, _VP],
             "hentt_ntt_inv": [_VP, _VP, _U32, _VP],
             "hentt_dyadic_mul": [_VP, _VP, _VP, _VP, _U32, _VP],
             "hentt_polymul": [_VP, _VP, _VP, _VP, _U32, _VP],
@@ -202,6 +204,23 @@ def ntt_fwd(tables, x, stream=None):
     _check(lib().hentt_ntt_fwd(tables.handle, _words(x, "x"), _batch_of(tables, x), _stream(stream)),
            "hentt_ntt_fwd")
     return x
+
+
+def rescale(tables, c, out=None, ntt=False, stream=None):
+    """Rescale (RS of section II-A): c [batch, limbs, N] at the tables' level
+    (limbs >= 2) -> [batch, limbs - 1, N] = round(c / q_last) per remaining
+    limb.  ntt: NTT-domain input and output (else coefficient domain)."""
+    if c.dim() != 3:
+        raise HenttError("c must have shape [batch, limbs, N]")
+    batch = _batch_of(tables, c, name="c")
+    if out is None:
+        out = torch.empty((batch, tables.limbs - 1, tables.n), dtype=c.dtype, device=c.device)
+    elif tuple(out.shape) != (batch, tables.limbs - 1, tables.n):
+        raise HenttError("out must have shape [%d, %d, %d]" % (batch, tables.limbs - 1, tables.n))
+    flags = (HENTT_IN_NTT | HENTT_OUT_NTT) if ntt else 0
+    _check(lib().hentt_rescale(tables.handle, _words(c, "c"), _words(out, "out"), batch, flags, _stream(stream)),
+           "hentt_rescale")
+    return out
 
 
 # Kernel designs of hentt_ntt_fwd_variant (the ladder of section III-B).

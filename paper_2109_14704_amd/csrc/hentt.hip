@@ -15,6 +15,7 @@
 #include "../../include/hentt.h"
 #include "ntt_kernels.hpp"
 #include "batch_kernels.hpp"
+#include "rescale_kernels.hpp"
 
 using namespace hentt;
 
@@ -113,6 +114,8 @@ struct Storage {
   LimbConst *d_lc = nullptr;   // [limbs]
   std::vector<uint64_t> moduli;
   int device = 0;
+  std::mutex rs_mu;            // rescale constants per level (limb count), made on first use
+  std::map<uint32_t, RsLimb *> rs;
 };
 
 void release(Storage *s) {
@@ -122,6 +125,7 @@ void release(Storage *s) {
     (void)hipSetDevice(s->device);
     if (s->d_tw) (void)hipFree(s->d_tw);
     if (s->d_lc) (void)hipFree(s->d_lc);
+    for (auto &kv : s->rs) (void)hipFree(kv.second);
     (void)hipSetDevice(cur);
     delete s;
   }
@@ -542,6 +546,110 @@ int run_fwd_variant(const hentt_tables *t, uint64_t *x, uint32_t batch, int vari
   return HENTT_OK;
 }
 
+// ---------------------------------------------------------------- rescale
+// Constants of RS from a level of `level` limbs to level - 1 (section II-A):
+// per remaining limb i, floor(2^64 / q_i), q_i - (h mod q_i) with
+// h = (qL - 1) / 2, and qL^-1 mod q_i with its Shoup quotient.  Made once per
+// (tables, level) with a synchronous upload, like the tables themselves.
+int rs_constants(Storage *s, uint32_t level, const RsLimb **out) {
+  std::lock_guard<std::mutex> lk(s->rs_mu);
+  auto it = s->rs.find(level);
+  if (it != s->rs.end()) {
+    *out = it->second;
+    return HENTT_OK;
+  }
+  const uint32_t L = level - 1;
+  const uint64_t qL = s->moduli[L], h = (qL - 1) / 2;
+  std::vector<RsLimb> host(L);
+  for (uint32_t i = 0; i < L; ++i) {
+    const uint64_t q = s->moduli[i];
+    host[i].mu = (uint64_t)(((u128)1 << 64) / q);
+    host[i].nh = q - h % q;
+    host[i].w = h_pow(qL % q, q - 2, q);
+    host[i].ws = shoup_quot(host[i].w, q);
+  }
+  RsLimb *d = nullptr;
+  hipError_t e = hipMalloc(&d, L * sizeof(RsLimb));
+  if (e == hipSuccess) e = hipMemcpy(d, host.data(), L * sizeof(RsLimb), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    if (d) (void)hipFree(d);
+    return hip_fail(e);
+  }
+  s->rs[level] = d;
+  *out = d;
+  return HENTT_OK;
+}
+
+template <int LOGN> void launch_rescale_ntt(const RsArgs &a, const Storage *s, hipStream_t st) {
+  const uint32_t units = a.batch * a.L;
+  using P = Plan<LOGN>;
+  if constexpr (P::WHOLE) {
+    LaunchTimer lt_("k_rs_whole", LOGN, st);
+    hipLaunchKernelGGL((k_rs_whole<LOGN, 4>), dim3(units), dim3(1 << (LOGN - 4)), 0, st, a, s->d_tw, s->d_lc);
+  } else {
+    {
+      LaunchTimer lt_("k_rs_cols", LOGN, st);
+      hipLaunchKernelGGL((k_rs_cols<LOGN, P::EC>), dim3(units * ((1u << (LOGN - P::EC)) / 256)), dim3(256), 0, st, a,
+                         s->d_tw, s->d_lc);
+    }
+    LaunchTimer lt_("k_rs_blocks", LOGN, st);
+    hipLaunchKernelGGL((k_rs_blocks<LOGN, P::B, 4>), dim3(units << (LOGN - P::B)), dim3(1 << (P::B - 4)), 0, st, a,
+                       s->d_tw, s->d_lc);
+  }
+}
+typedef void (*rs_fn)(const RsArgs &, const Storage *, hipStream_t);
+#define RS_ENTRY(n) launch_rescale_ntt<n>,
+const rs_fn k_rs_table[] = {HENTT_SIZES(RS_ENTRY)};
+
+int run_rescale(const hentt_tables *t, const uint64_t *c, uint64_t *out, uint32_t batch, bool ntt, hipStream_t st) {
+  Storage *s = t->s;
+  const uint32_t ln = s->log_n, level = t->limbs, L = level - 1;
+  const uint64_t N = 1ull << ln;
+  const RsLimb *rs = nullptr;
+  int rc = rs_constants(s, level, &rs);
+  if (rc) return rc;
+  RsArgs a{};
+  a.c = c;
+  a.out = out;
+  a.rs = rs;
+  a.qL = s->moduli[L];
+  a.h = (a.qL - 1) / 2;
+  a.batch = batch;
+  a.L = L;
+  if (!ntt) {
+    const uint32_t tiles = (uint32_t)((N + 2047) / 2048);
+    LaunchTimer lt_("k_rs_coeff", (int)ln, st);
+    hipLaunchKernelGGL(k_rs_coeff, dim3(batch * L * tiles), dim3(256), 0, st, a, s->d_lc, ln, tiles);
+    HIPCHK(hipGetLastError());
+    return HENTT_OK;
+  }
+  // the last limb of every batch entry, inverse-transformed modulo qL
+  void *tl = nullptr;
+  rc = pool_get((size_t)batch * N * 8, st, &tl);
+  if (rc) return rc;
+  hipError_t e = hipMemcpy2DAsync(tl, N * 8, c + (size_t)L * N, (size_t)level * N * 8, N * 8, batch,
+                                  hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) {
+    Storage last;  // limb L's tables alone (a view: owns nothing)
+    last.log_n = ln;
+    last.limbs = 1;
+    last.d_tw = s->d_tw + (size_t)L * 2 * N;
+    last.d_lc = s->d_lc + L;
+    last.device = s->device;
+    const hentt_tables lv{&last, 1};
+    rc = run_transform(&lv, (uint64_t *)tl, batch, st, true);
+    if (!rc) {
+      a.tl = (const uint64_t *)tl;
+      k_rs_table[ln - HENTT_LOG_N_MIN](a, s, st);
+      e = hipGetLastError();
+    }
+  }
+  pool_put(tl);
+  if (rc) return rc;
+  if (e != hipSuccess) return hip_fail(e);
+  return HENTT_OK;
+}
+
 int run_prod(const hentt_tables *t, int mode, const ProdArgs &pa, uint32_t batch, bool in_coeff, bool out_coeff,
              hipStream_t st) {
   const int ln = (int)t->s->log_n;
@@ -738,6 +846,18 @@ int hentt_ntt_fwd(const hentt_tables *t, uint64_t *x, uint32_t batch, void *stre
 int hentt_ntt_fwd_variant(const hentt_tables *t, uint64_t *x, uint32_t batch, int variant, void *stream) {
   if (!t || !x || batch == 0) return HENTT_EINVAL;
   return run_fwd_variant(t, x, batch, variant, (hipStream_t)stream);
+}
+
+int hentt_rescale(const hentt_tables *t, const uint64_t *c, uint64_t *out, uint32_t batch, uint32_t flags,
+                  void *stream) {
+  if (!t || !c || !out || batch == 0 || t->limbs < 2) return HENTT_EINVAL;
+  const bool ntt = flags == (HENTT_IN_NTT | HENTT_OUT_NTT);
+  if (!ntt && flags != 0) return HENTT_EINVAL;
+  const uint64_t N = 1ull << t->s->log_n;
+  const uintptr_t c0 = (uintptr_t)c, c1 = c0 + (uintptr_t)(batch * (uint64_t)t->limbs * N * 8);
+  const uintptr_t o0 = (uintptr_t)out, o1 = o0 + (uintptr_t)(batch * (uint64_t)(t->limbs - 1) * N * 8);
+  if (o0 < c1 && c0 < o1) return HENTT_EINVAL;  // out overlaps c
+  return run_rescale(t, c, out, batch, ntt, (hipStream_t)stream);
 }
 
 int hentt_ntt_inv(const hentt_tables *t, uint64_t *x, uint32_t batch, void *stream) {

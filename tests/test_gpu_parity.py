@@ -139,6 +139,48 @@ def test_design_ladder_rejects(gpu):
             H.ntt_fwd_variant(t, x, variant)
 
 
+@pytest.mark.parametrize("log_n", [6, 12, 14, 15, 16, 17])
+@pytest.mark.parametrize("limbs", [2, 4])
+def test_rescale(gpu, log_n, limbs):
+    """Rescale (RS, section II-A) in both domains, element by element."""
+    import paper_2109_14704_amd as H
+    print("case rescale log_n=%d limbs=%d" % (log_n, limbs), flush=True)
+    mods = CHAIN[:limbs]
+    rng = np.random.default_rng(500 + 3 * log_n + limbs)
+    t = H.Tables(log_n, mods)
+    x = rand_limbs(rng, (3, limbs, 1 << log_n), mods)
+    got = H.rescale(t, dev(x, gpu))
+    assert np.array_equal(host(got), oracle.batch_rescale(x, mods))
+    X = oracle.batch_ntt(x, mods, +1)
+    Xd = dev(X, gpu)
+    got = H.rescale(t, Xd, ntt=True)
+    assert np.array_equal(host(got), oracle.batch_rescale_ntt(X, mods))
+    assert np.array_equal(host(Xd), X)                       # input untouched
+
+
+def test_rescale_level_views_and_errors(gpu):
+    """A level view rescales by its own last prime; bad calls are refused."""
+    import paper_2109_14704_amd as H
+    mods = workloads.moduli("ct_tensor")[:5]
+    t = H.Tables(15, mods)
+    v = t.view(3)
+    rng = np.random.default_rng(9)
+    x = rand_limbs(rng, (2, 3, 1 << 15), mods[:3])
+    got = H.rescale(v, dev(x, gpu), ntt=True)
+    assert np.array_equal(host(got), oracle.batch_rescale_ntt(x, mods[:3]))
+    one = t.view(1)
+    with pytest.raises(H.HenttError):
+        H.rescale(one, dev(x[:, :1], gpu))
+    xd = dev(x, gpu)
+    alias = xd.view(-1)[: 2 * 2 * (1 << 15)].view(2, 2, 1 << 15)
+    with pytest.raises(H.HenttError):                        # out overlapping c (refused by the library)
+        H.rescale(v, xd, out=alias)
+    import ctypes
+    rc = H.lib().hentt_rescale(v.handle, ctypes.c_void_p(xd.data_ptr()), ctypes.c_void_p(dev(x, gpu).data_ptr()),
+                               2, H.HENTT_IN_NTT, None)
+    assert rc != 0                                           # only both-or-neither NTT flags
+
+
 def test_plain4096_workload(gpu):
     """Workload 1 at full size: 8 polys fwd + inv, one polymul vs schoolbook."""
     import paper_2109_14704_amd as H
