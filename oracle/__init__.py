@@ -69,6 +69,7 @@ def lib():
             "or_batch_dyadic": (None, [P64, P64, P64, U32, U32, U32, P64]),
             "or_batch_tensor": (None, [P64, P64, P64, U32, U32, U32, P64]),
             "or_batch_rescale": (None, [P64, P64, U32, U32, U32, P64]),
+            "or_ct_matmul": (None, [P64, P64, P64, U32, U32, U32, U32, U32, P64]),
             "or_batch_polymul": (ctypes.c_int, [P64, P64, P64, U32, U32, U32, P64, ctypes.c_int]),
             "or_batch_ct_tensor_coeff": (ctypes.c_int, [P64, P64, P64, U32, U32, U32, P64, ctypes.c_int]),
         }
@@ -233,6 +234,18 @@ def batch_rescale_ntt(c, moduli):
     limbs = c.shape[1]
     x = batch_ntt(c, moduli[:limbs], -1)
     return batch_ntt(batch_rescale(x, moduli[:limbs]), moduli[:limbs - 1], +1)
+
+
+def ct_matmul(A, B, C, moduli):
+    """C + A * B for ciphertext matrices in the NTT domain (section IV-E):
+    A [m][k][2][limbs][N], B [k][n][2][limbs][N], C [m][n][3][limbs][N]."""
+    A = _u64(A); B = _u64(B); out = _u64(C).copy(); m_ = _moduli(moduli)
+    m, k, _, limbs, n_ = A.shape
+    n = B.shape[1]
+    if B.shape != (k, n, 2, limbs, n_) or out.shape != (m, n, 3, limbs, n_):
+        raise ValueError("oracle: matmul shapes")
+    lib().or_ct_matmul(_p(A), _p(B), _p(out), m, n, k, limbs, n_, _p(m_[:limbs]))
+    return out
 
 
 def max_threads():

@@ -391,3 +391,27 @@ void or_batch_rescale(const uint64_t *x, uint64_t *out, uint32_t batch, uint32_t
       }
     }
 }
+
+/* Encrypted element-wise polynomial matrix product (section IV-E), NTT domain:
+ * C (m x n) += A (m x k) * B (k x n), every element a ciphertext and every
+ * element product the Mul tensor of section II-A, accumulated over k:
+ *   C_ij = C_ij + sum_l (a0 b0, a0 b1 + a1 b0, a1 b1),  a = A_il, b = B_lj.
+ * A [m][k][2][limbs][N], B [k][n][2][limbs][N], C [m][n][3][limbs][N]. */
+void or_ct_matmul(const uint64_t *A, const uint64_t *B, uint64_t *C, uint32_t m, uint32_t n, uint32_t k,
+                  uint32_t limbs, uint32_t N, const uint64_t *moduli) {
+  const size_t P = (size_t)limbs * N;
+  for (uint32_t i = 0; i < m; ++i)
+    for (uint32_t j = 0; j < n; ++j) {
+      uint64_t *c0 = C + ((size_t)i * n + j) * 3 * P, *c1 = c0 + P, *c2 = c1 + P;
+      for (uint32_t l = 0; l < k; ++l) {
+        const uint64_t *a0 = A + ((size_t)i * k + l) * 2 * P, *a1 = a0 + P;
+        const uint64_t *b0 = B + ((size_t)l * n + j) * 2 * P, *b1 = b0 + P;
+        for (size_t e = 0; e < P; ++e) {
+          const uint64_t q = moduli[e / N];
+          c0[e] = or_addmod(c0[e], or_mulmod(a0[e], b0[e], q), q);
+          c1[e] = or_addmod(c1[e], or_addmod(or_mulmod(a0[e], b1[e], q), or_mulmod(a1[e], b0[e], q), q), q);
+          c2[e] = or_addmod(c2[e], or_mulmod(a1[e], b1[e], q), q);
+        }
+      }
+    }
+}

@@ -343,3 +343,36 @@ def test_rescale_ntt_domain_is_linear_and_scales_by_the_dropped_prime():
     X = oracle.batch_ntt(x, mods, +1)
     got = oracle.batch_rescale_ntt(X, mods)
     assert np.array_equal(got, oracle.batch_ntt(y, mods[:2], +1))
+
+
+# ----------------------------------------------------------------- matMul --
+def test_ct_matmul_matches_schoolbook_products():
+    """C += A*B over ciphertexts in the NTT domain (section IV-E) equals, after
+    the inverse transform, the coefficient-domain sum of negacyclic schoolbook
+    tensor products: the convolution theorem, not the oracle's own formula."""
+    import workloads
+    mods = workloads.moduli("uneven")[:2]
+    n, m, nn, k = 32, 2, 3, 2
+    rng = np.random.default_rng(11)
+    def coeff(shape):
+        out = np.empty(shape + (2, n), dtype=np.uint64)
+        for l, q in enumerate(mods):
+            out[..., l, :] = rng.integers(0, q, size=shape + (n,), dtype=np.uint64)
+        return out
+    a, b, c = coeff((m, k, 2)), coeff((k, nn, 2)), coeff((m, nn, 3))
+    ntt = lambda x: oracle.batch_ntt(x.reshape(-1, 2, n), mods, +1).reshape(x.shape)
+    got = oracle.ct_matmul(ntt(a), ntt(b), ntt(c), mods)
+    got = oracle.batch_ntt(got.reshape(-1, 2, n), mods, -1).reshape(got.shape)
+    for i in range(m):
+        for j in range(nn):
+            for li, q in enumerate(mods):
+                want = [c[i, j, s, li].astype(object) for s in range(3)]
+                for l in range(k):
+                    x0, x1 = a[i, l, 0, li], a[i, l, 1, li]
+                    y0, y1 = b[l, j, 0, li], b[l, j, 1, li]
+                    p = lambda u, v: oracle.negacyclic_schoolbook(u, v, q).astype(object)
+                    want[0] = (want[0] + p(x0, y0)) % q
+                    want[1] = (want[1] + p(x0, y1) + p(x1, y0)) % q
+                    want[2] = (want[2] + p(x1, y1)) % q
+                for s in range(3):
+                    assert np.array_equal(got[i, j, s, li].astype(object), want[s]), (i, j, s, li)
