@@ -31,7 +31,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20,
                     help="untimed steps; the clocks settle after about 20 steps of the default workload")
     ap.add_argument("--workload", default="ckks_level",
-                    choices=["ckks_level", "ct_tensor", "plain4096", "uneven", "serving", "ladder", "rescale"])
+                    choices=["ckks_level", "ct_tensor", "plain4096", "uneven", "serving", "ladder", "rescale",
+                             "matmul"])
     ap.add_argument("--requests", type=int, default=2200, help="serving: requests per trace (first 200 warm up)")
     ap.add_argument("--grid", type=int, default=0, help="persistent workgroups for the uneven batch (0 = tuned/default)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -248,6 +249,7 @@ VALU_BFLY = 21     # Harvey/Shoup butterfly: 9 32-bit multiplies + 12 adds, comp
 VALU_PROD = 38     # Barrett product a*b mod q: 128-bit product, quotient estimate, 3 corrections
 VALU_TENSOR = 121  # c0d0, c1d1 (2 x 38) + c0d1 + c1d0 with one reduction (45)
 VALU_RS_EPI = 17   # rescale epilogue: Shoup product by qL^-1 (9 + adds) and a reduction from [0, 4q)
+VALU_MAC = 121     # one matMul product term: the tensor's three outputs accumulated with mad_mod
 
 
 def kernel_work(name, info):
@@ -394,6 +396,66 @@ def bench_ladder(args):
     print(json.dumps(result), flush=True)
 
 
+def bench_matmul(args):
+    """The paper's encrypted element-wise polynomial matMul shapes (section
+    IV-E): C += A*B with ciphertext elements of N = 8192 over 4 limbs, NTT
+    domain, 100x100x1 and 10x9x8 (m x n x k).  Value: element ciphertext
+    products per second on 100x100x1.  Roofline against the compulsory bytes
+    (A and B once, C read and written) and VALU_MAC ops per product term."""
+    import torch
+    import workloads
+    import paper_2109_14704_amd as H
+    from paper_2109_14704_amd import roofline as R
+    mods = workloads.moduli("ct_tensor")[:4]
+    L, logn = len(mods), 13
+    n_ = 1 << logn
+    t = H.Tables(logn, mods)
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(2109_14704 + 8)
+
+    def operand(shape):
+        x = torch.empty(shape + (L, n_), dtype=torch.int64, device="cuda:0")
+        for l, q in enumerate(mods):
+            x[..., l, :].copy_(torch.randint(0, q, shape + (n_,), generator=gen, device="cuda:0", dtype=torch.int64))
+        return x
+
+    rows = []
+    for (m, n, k) in [(100, 100, 1), (10, 9, 8)]:
+        A, B, C = operand((m, k, 2)), operand((k, n, 2)), operand((m, n, 3))
+        for _ in range(max(2, args.warmup // 4)):
+            H.ct_matmul(t, A, B, C)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = max(3, args.steps // 3)
+        a.record()
+        for _ in range(reps):
+            H.ct_matmul(t, A, B, C)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        nbytes = 8.0 * L * n_ * (2 * m * k + 2 * k * n + 6 * m * n)
+        ops = float(VALU_MAC) * m * n * k * L * n_
+        t_hbm, t_alu = nbytes / (R.HBM_PEAK_GBS * 1e9), ops / (R.VALU_PEAK_TOPS * 1e12)
+        if t_hbm >= t_alu:
+            rl = {"bound": "hbm", "achieved": round(nbytes / ms / 1e6, 1), "peak": R.HBM_PEAK_GBS, "unit": "GB/s",
+                  "frac": round(nbytes / ms / 1e6 / R.HBM_PEAK_GBS, 4)}
+        else:
+            rl = {"bound": "alu", "achieved": round(ops / ms / 1e9, 3), "peak": round(R.VALU_PEAK_TOPS, 2),
+                  "unit": "T VALU-op/s", "frac": round(ops / ms / 1e9 / R.VALU_PEAK_TOPS, 4)}
+        rl.update({"kernel": "k_ct_matmul<13>", "launch_ms": round(ms, 4), "traffic": R.stored_traffic("k_ct_matmul<13>")})
+        rows.append({"shape": "%dx%dx%d" % (m, n, k), "ms": round(ms, 4),
+                     "element_products_per_s": round(m * n * k / ms * 1e3, 1), "roofline": rl})
+        del A, B, C
+    first = rows[0]
+    info = {"workload": "matmul", "N": n_, "limbs": L, "shapes": [r["shape"] for r in rows],
+            "ops": "C += A*B, ciphertext elements, NTT domain, mad_mod accumulation"}
+    result = {"metric": METRIC, "value": first["element_products_per_s"], "unit": "ct element products/s",
+              "n_gpus": 1, "steps": max(3, args.steps // 3), "warmup": max(2, args.warmup // 4),
+              "ms_per_step": first["ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+              "dtype": "u64", "data": "synthetic", "config": info, "roofline": first["roofline"], "shapes": rows}
+    print(json.dumps(result), flush=True)
+
+
 def bench_serving(args):
     """Poisson ct-mul serving: saturation throughput, then p50/p99 latency of the
     continuous-batching server and of per-request launches on the same traces
@@ -462,6 +524,11 @@ def bench_serving(args):
 
 def main():
     args = parse()
+    if args.workload == "matmul":
+        if args.gpus != 1:
+            print("bench.py: one GPU only", file=sys.stderr)
+            sys.exit(2)
+        return bench_matmul(args)
     if args.workload == "ladder":
         if args.gpus != 1:
             print("bench.py: one GPU only", file=sys.stderr)

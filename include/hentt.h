@@ -110,6 +110,18 @@ int hentt_ntt_fwd(const hentt_tables *t, uint64_t *x, uint32_t batch, void *stre
 int hentt_rescale(const hentt_tables *t, const uint64_t *c, uint64_t *out, uint32_t batch, uint32_t flags,
                   void *stream);
 
+/* Encrypted element-wise polynomial matrix product of section IV-E, NTT
+ * domain: C (m x n) += A (m x k) * B (k x n) where every matrix element is a
+ * ciphertext and every element product the Mul tensor of section II-A
+ * (c0 d0, c0 d1 + c1 d0, c1 d1), accumulated over k with one modular
+ * reduction per multiply-add (mad_mod, section III-A-1).
+ * A [m][k][2][limbs][N], B [k][n][2][limbs][N], C [m][n][3][limbs][N] with
+ * limbs and N those of t; canonical inputs, canonical C.  C is updated in
+ * place and must not overlap A or B.  HENTT_EINVAL for null pointers, a zero
+ * dimension, overlap, or more than 2^31 - 1 workgroups (m n limbs N / 2048). */
+int hentt_ct_matmul(const hentt_tables *t, const uint64_t *A, const uint64_t *B, uint64_t *C, uint32_t m, uint32_t n,
+                    uint32_t k, void *stream);
+
 /* Kernel-design ladder of the forward transform (section III-B and the
  * NTT evaluation of section IV): the same result as hentt_ntt_fwd, computed
  * by reference kernel designs so that they can be timed against each other.

@@ -13,7 +13,7 @@ import torch
 
 __all__ = ["HenttError", "Tables", "ntt_fwd", "ntt_inv", "dyadic_mul", "polymul", "ct_tensor", "ntt_batch",
            "psi", "lib", "LIB_PATH", "prof_enable", "prof_read", "BatchPlan", "stage_split", "ntt_fwd_variant",
-           "rescale"]
+           "rescale", "ct_matmul"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("HENTT_LIB") or os.path.join(_HERE, "libhentt.so")  # HENTT_LIB: alternative build
@@ -53,6 +53,7 @@ def lib():
             "hentt_ntt_fwd": [_VP, _VP, _U32, _VP],
             "hentt_ntt_fwd_variant": [_VP, _VP, _U32, ctypes.c_int, _VP],
             "hentt_rescale": [_VP, _VP, _VP, _U32, _U32, _VP],
+            "hentt_ct_matmul": [_VP, _VP, _VP, _VP, _U32, _U32, _U32, _VP],
             "hentt_ntt_inv": [_VP, _VP, _U32, _VP],
             "hentt_dyadic_mul": [_VP, _VP, _VP, _VP, _U32, _VP],
             "hentt_polymul": [_VP, _VP, _VP, _VP, _U32, _VP],
@@ -221,6 +222,22 @@ def rescale(tables, c, out=None, ntt=False, stream=None):
     _check(lib().hentt_rescale(tables.handle, _words(c, "c"), _words(out, "out"), batch, flags, _stream(stream)),
            "hentt_rescale")
     return out
+
+
+def ct_matmul(tables, A, B, C, stream=None):
+    """C += A * B for ciphertext matrices in the NTT domain (section IV-E):
+    A [m, k, 2, limbs, N], B [k, n, 2, limbs, N], C [m, n, 3, limbs, N]; C in place."""
+    L, n_ = tables.limbs, tables.n
+    if A.dim() != 5 or B.dim() != 5 or C.dim() != 5:
+        raise HenttError("A, B, C must be 5-dimensional ciphertext matrices")
+    m, k = A.shape[0], A.shape[1]
+    n = B.shape[1]
+    if (tuple(A.shape) != (m, k, 2, L, n_) or tuple(B.shape) != (k, n, 2, L, n_)
+            or tuple(C.shape) != (m, n, 3, L, n_)):
+        raise HenttError("shapes: A [m,k,2,%d,%d], B [k,n,2,%d,%d], C [m,n,3,%d,%d]" % (L, n_, L, n_, L, n_))
+    _check(lib().hentt_ct_matmul(tables.handle, _words(A, "A"), _words(B, "B"), _words(C, "C"), m, n, k,
+                                 _stream(stream)), "hentt_ct_matmul")
+    return C
 
 
 # Kernel designs of hentt_ntt_fwd_variant (the ladder of section III-B).

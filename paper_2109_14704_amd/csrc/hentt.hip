@@ -860,6 +860,25 @@ int hentt_rescale(const hentt_tables *t, const uint64_t *c, uint64_t *out, uint3
   return run_rescale(t, c, out, batch, ntt, (hipStream_t)stream);
 }
 
+int hentt_ct_matmul(const hentt_tables *t, const uint64_t *A, const uint64_t *B, uint64_t *C, uint32_t m, uint32_t n,
+                    uint32_t k, void *stream) {
+  if (!t || !A || !B || !C || m == 0 || n == 0 || k == 0) return HENTT_EINVAL;
+  const uint64_t N = 1ull << t->s->log_n, P = (uint64_t)t->limbs * N;
+  const uintptr_t c0 = (uintptr_t)C, c1 = c0 + (uintptr_t)((uint64_t)m * n * 3 * P * 8);
+  const uintptr_t a0 = (uintptr_t)A, a1 = a0 + (uintptr_t)((uint64_t)m * k * 2 * P * 8);
+  const uintptr_t b0 = (uintptr_t)B, b1 = b0 + (uintptr_t)((uint64_t)k * n * 2 * P * 8);
+  if ((c0 < a1 && a0 < c1) || (c0 < b1 && b0 < c1)) return HENTT_EINVAL;  // C overlaps an input
+  const uint32_t tiles = (uint32_t)((N + 2047) / 2048);
+  const uint64_t grid = (uint64_t)m * n * t->limbs * tiles;
+  if (grid > 0x7fffffffu) return HENTT_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  LaunchTimer lt_("k_ct_matmul", (int)t->s->log_n, st);
+  hipLaunchKernelGGL(k_ct_matmul, dim3((uint32_t)grid), dim3(256), 0, st, A, B, C, t->s->d_lc, m, n, k, t->limbs,
+                     t->s->log_n, tiles);
+  HIPCHK(hipGetLastError());
+  return HENTT_OK;
+}
+
 int hentt_ntt_inv(const hentt_tables *t, uint64_t *x, uint32_t batch, void *stream) {
   if (!t || !x || batch == 0) return HENTT_EINVAL;
   return run_transform(t, x, batch, (hipStream_t)stream, true);

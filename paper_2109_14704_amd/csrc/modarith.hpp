@@ -133,4 +133,24 @@ __device__ __forceinline__ uint64_t madmod(uint64_t a, uint64_t b, uint64_t c, u
   return barrett(h, l, q, mu, k);
 }
 
+// Multiply-accumulate with one reduction (mad_mod, section III-A-1):
+// (a b + e) mod q and (a b + c d + e) mod q for canonical inputs.  The sums
+// stay below 2 q^2 < 2^(2k+1), the Barrett bound above.
+__device__ __forceinline__ uint64_t mac1mod(uint64_t a, uint64_t b, uint64_t e, uint64_t q, uint64_t mu, uint32_t k) {
+  uint64_t h, l;
+  mul128(a, b, h, l);
+  const uint64_t s = l + e;
+  return barrett(h + (s < l ? 1 : 0), s, q, mu, k);
+}
+__device__ __forceinline__ uint64_t mac2mod(uint64_t a, uint64_t b, uint64_t c, uint64_t d, uint64_t e, uint64_t q,
+                                            uint64_t mu, uint32_t k) {
+  uint64_t h1, l1, h2, l2;
+  mul128(a, b, h1, l1);
+  mul128(c, d, h2, l2);
+  const uint64_t l = l1 + l2;
+  const uint64_t h = h1 + h2 + (l < l1 ? 1 : 0);
+  const uint64_t s = l + e;
+  return barrett(h + (s < l ? 1 : 0), s, q, mu, k);
+}
+
 }  // namespace hentt

@@ -559,6 +559,62 @@ __global__ __launch_bounds__(1 << (B - E)) void k_prod(ProdArgs a, const Tw *__r
   }
 }
 
+// Encrypted element-wise polynomial matrix product (section IV-E), NTT
+// domain: C (m x n) += A (m x k) * B (k x n) with ciphertext elements, every
+// element product the Mul tensor accumulated with one reduction per
+// multiply-add.  One workgroup per (limb, i, j, tile of 2048 coefficients),
+// j and the tile fastest so that consecutive workgroups share A's tiles in
+// L2; 8 coefficients per lane, the three accumulators in registers over k.
+__global__ __launch_bounds__(256) void k_ct_matmul(const uint64_t *__restrict__ A, const uint64_t *__restrict__ B,
+                                                   uint64_t *__restrict__ C, const LimbConst *__restrict__ lc,
+                                                   uint32_t m, uint32_t n, uint32_t k, uint32_t limbs,
+                                                   uint32_t log_n, uint32_t tiles) {
+  uint32_t r = blockIdx.x;
+  const uint32_t tile = r % tiles;
+  r /= tiles;
+  const uint32_t j = r % n;
+  r /= n;
+  const uint32_t i = r % m, limb = r / m;
+  const LimbConst cst = lc[limb];
+  const uint64_t q = cst.m.q, mu = cst.mu;
+  const uint32_t kb = cst.k, N = 1u << log_n;
+  const uint64_t P = (uint64_t)limbs << log_n;
+  const uint64_t off = ((uint64_t)limb << log_n) + tile * 2048u;
+  uint64_t *c = C + ((uint64_t)i * n + j) * 3 * P + off;
+  uint64_t c0[8], c1[8], c2[8];
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const uint32_t e = threadIdx.x + 256u * s;
+    const bool in = tile * 2048u + e < N;
+    c0[s] = in ? c[e] : 0;
+    c1[s] = in ? c[P + e] : 0;
+    c2[s] = in ? c[2 * P + e] : 0;
+  }
+  for (uint32_t l = 0; l < k; ++l) {
+    const uint64_t *a = A + ((uint64_t)i * k + l) * 2 * P + off;
+    const uint64_t *b = B + ((uint64_t)l * n + j) * 2 * P + off;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const uint32_t e = threadIdx.x + 256u * s;
+      if (tile * 2048u + e < N) {
+        const uint64_t a0 = a[e], a1 = a[P + e], b0 = b[e], b1 = b[P + e];
+        c0[s] = mac1mod(a0, b0, c0[s], q, mu, kb);
+        c1[s] = mac2mod(a0, b1, a1, b0, c1[s], q, mu, kb);
+        c2[s] = mac1mod(a1, b1, c2[s], q, mu, kb);
+      }
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const uint32_t e = threadIdx.x + 256u * s;
+    if (tile * 2048u + e < N) {
+      c[e] = c0[s];
+      c[P + e] = c1[s];
+      c[2 * P + e] = c2[s];
+    }
+  }
+}
+
 // Element-wise products of NTT-domain inputs (no transform): tiles of 2048
 // words of one (batch entry, limb), coalesced, limb constants uniform per
 // workgroup.

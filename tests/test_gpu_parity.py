@@ -181,6 +181,39 @@ def test_rescale_level_views_and_errors(gpu):
     assert rc != 0                                           # only both-or-neither NTT flags
 
 
+@pytest.mark.parametrize("m,n,k,log_n", [(2, 3, 2, 13), (5, 4, 1, 12), (10, 9, 8, 6), (3, 2, 3, 13)])
+def test_ct_matmul(gpu, m, n, k, log_n):
+    """Encrypted element-wise polynomial matrix product, element by element."""
+    import paper_2109_14704_amd as H
+    print("case matmul %dx%dx%d log_n=%d" % (m, n, k, log_n), flush=True)
+    mods = workloads.moduli("ct_tensor")[:4]
+    rng = np.random.default_rng(600 + m * n * k + log_n)
+    A = rand_limbs(rng, (m, k, 2, 4, 1 << log_n), mods)
+    B = rand_limbs(rng, (k, n, 2, 4, 1 << log_n), mods)
+    C = rand_limbs(rng, (m, n, 3, 4, 1 << log_n), mods)
+    t = H.Tables(log_n, mods)
+    Cd = dev(C, gpu)
+    H.ct_matmul(t, dev(A, gpu), dev(B, gpu), Cd)
+    assert np.array_equal(host(Cd), oracle.ct_matmul(A, B, C, mods))
+
+
+def test_ct_matmul_paper_shape_sampled(gpu):
+    """100 x 100 x 1 at N = 8192, 4 limbs (the paper's first matMul shape):
+    sampled output elements against the oracle."""
+    import paper_2109_14704_amd as H
+    mods = workloads.moduli("ct_tensor")[:4]
+    rng = np.random.default_rng(601)
+    A = rand_limbs(rng, (100, 1, 2, 4, 8192), mods)
+    B = rand_limbs(rng, (1, 100, 2, 4, 8192), mods)
+    t = H.Tables(13, mods)
+    import torch
+    Cd = torch.zeros((100, 100, 3, 4, 8192), dtype=torch.int64, device=gpu)
+    H.ct_matmul(t, dev(A, gpu), dev(B, gpu), Cd)
+    for i, j in [(0, 0), (99, 99), (17, 42), (63, 5)]:
+        want = oracle.ct_matmul(A[i:i + 1], B[:, j:j + 1], np.zeros((1, 1, 3, 4, 8192), np.uint64), mods)
+        assert np.array_equal(host(Cd[i:i + 1, j:j + 1]), want), (i, j)
+
+
 def test_plain4096_workload(gpu):
     """Workload 1 at full size: 8 polys fwd + inv, one polymul vs schoolbook."""
     import paper_2109_14704_amd as H
