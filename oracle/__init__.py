@@ -70,6 +70,7 @@ def lib():
             "or_batch_tensor": (None, [P64, P64, P64, U32, U32, U32, P64]),
             "or_batch_rescale": (None, [P64, P64, U32, U32, U32, P64]),
             "or_ct_matmul": (None, [P64, P64, P64, U32, U32, U32, U32, U32, P64]),
+            "or_relin": (ctypes.c_int, [P64, P64, P64, U32, U32, U32, P64, ctypes.c_int]),
             "or_batch_polymul": (ctypes.c_int, [P64, P64, P64, U32, U32, U32, P64, ctypes.c_int]),
             "or_batch_ct_tensor_coeff": (ctypes.c_int, [P64, P64, P64, U32, U32, U32, P64, ctypes.c_int]),
         }
@@ -245,6 +246,21 @@ def ct_matmul(A, B, C, moduli):
     if B.shape != (k, n, 2, limbs, n_) or out.shape != (m, n, 3, limbs, n_):
         raise ValueError("oracle: matmul shapes")
     lib().or_ct_matmul(_p(A), _p(B), _p(out), m, n, k, limbs, n_, _p(m_[:limbs]))
+    return out
+
+
+def relin(c, ksk, moduli, threads=0):
+    """Relinearization of section II-A with the RNS digit decomposition, NTT
+    domain: c [batch][3][l][N], ksk [l][2][l + 1][N] over moduli[:l + 1] (the
+    last one the special prime P) -> [batch][2][l][N]."""
+    c = _u64(c); ksk = _u64(ksk); m = _moduli(moduli)
+    batch, three, l, n = c.shape
+    if three != 3 or ksk.shape != (l, 2, l + 1, n) or len(m) < l + 1:
+        raise ValueError("oracle: relin shapes")
+    out = np.zeros((batch, 2, l, n), dtype=np.uint64)
+    rc = lib().or_relin(_p(c), _p(ksk), _p(out), batch, l, n.bit_length() - 1, _p(m[:l + 1]), int(threads))
+    if rc:
+        raise ValueError("oracle: bad modulus")
     return out
 
 

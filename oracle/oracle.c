@@ -415,3 +415,55 @@ void or_ct_matmul(const uint64_t *A, const uint64_t *B, uint64_t *C, uint32_t m,
       }
     }
 }
+
+/* Relinearization Relin (section II-A): c' = (c0, c1) + round(P^-1 c2 evk)
+ * mod q, with the RNS digit decomposition of c2 used by the key switch:
+ *   c2 evk = sum_j [c2]_{q_j} evk_j   over the extended basis q_0..q_{l-1}, P.
+ * Steps, in the NTT domain in and out (l = limbs of the ciphertext, moduli
+ * holds l + 1 primes, the last one P):
+ *   d_j = INTT_j(c2_j), integers in [0, q_j);
+ *   acc_s[t] = sum_j NTT_t(d_j mod q_t) . ksk[j][s][t]  mod q_t,  t <= l, s = 0, 1;
+ *   acc_s -> round(acc_s / P) over q_0..q_{l-1} (the rescale by P);
+ *   out_s = c_s + acc_s.
+ * c [batch][3][l][N], ksk [l][2][l + 1][N], out [batch][2][l][N]. */
+int or_relin(const uint64_t *c, const uint64_t *ksk, uint64_t *out, uint32_t batch, uint32_t l, uint32_t log_n,
+             const uint64_t *moduli, int threads) {
+  const uint32_t N = 1u << log_n, L1 = l + 1;
+  const size_t P = (size_t)l * N, PE = (size_t)L1 * N;
+  uint64_t *d = (uint64_t *)malloc((size_t)batch * P * 8);
+  uint64_t *e = (uint64_t *)malloc(PE * 8);
+  uint64_t *acc = (uint64_t *)calloc((size_t)batch * 2 * PE, 8);
+  uint64_t *lo = (uint64_t *)malloc((size_t)batch * 2 * P * 8);
+  int rc = 0;
+  for (uint32_t b = 0; b < batch; ++b) memcpy(d + b * P, c + ((size_t)b * 3 + 2) * P, P * 8);
+  rc = or_batch_ntt(d, batch, l, log_n, moduli, -1, threads);
+  for (uint32_t b = 0; b < batch && !rc; ++b)
+    for (uint32_t j = 0; j < l && !rc; ++j) {
+      const uint64_t *dj = d + b * P + (size_t)j * N;
+      for (uint32_t t = 0; t < L1; ++t)
+        for (uint32_t k = 0; k < N; ++k) e[(size_t)t * N + k] = dj[k] % moduli[t];
+      rc = or_batch_ntt(e, 1, L1, log_n, moduli, +1, threads);
+      for (uint32_t s = 0; s < 2 && !rc; ++s) {
+        uint64_t *a = acc + ((size_t)b * 2 + s) * PE;
+        const uint64_t *key = ksk + ((size_t)j * 2 + s) * PE;
+        for (size_t x = 0; x < PE; ++x) {
+          const uint64_t q = moduli[x / N];
+          a[x] = or_addmod(a[x], or_mulmod(e[x], key[x], q), q);
+        }
+      }
+    }
+  if (!rc) rc = or_batch_ntt(acc, batch * 2, L1, log_n, moduli, -1, threads);
+  if (!rc) {
+    or_batch_rescale(acc, lo, batch * 2, L1, N, moduli);
+    rc = or_batch_ntt(lo, batch * 2, l, log_n, moduli, +1, threads);
+  }
+  for (uint32_t b = 0; b < batch && !rc; ++b)
+    for (uint32_t s = 0; s < 2; ++s) {
+      const uint64_t *cs = c + ((size_t)b * 3 + s) * P;
+      const uint64_t *ls = lo + ((size_t)b * 2 + s) * P;
+      uint64_t *o = out + ((size_t)b * 2 + s) * P;
+      for (size_t x = 0; x < P; ++x) o[x] = or_addmod(cs[x], ls[x], moduli[x / N]);
+    }
+  free(d); free(e); free(acc); free(lo);
+  return rc;
+}

@@ -376,3 +376,53 @@ def test_ct_matmul_matches_schoolbook_products():
                     want[2] = (want[2] + p(x1, y1)) % q
                 for s in range(3):
                     assert np.array_equal(got[i, j, s, li].astype(object), want[s]), (i, j, s, li)
+
+
+# ------------------------------------------------------------------ relin --
+def test_relin_matches_big_integer_key_switch():
+    """Relin of section II-A, c' = (c0, c1) + round(P^-1 c2 evk) mod q, pinned
+    against a big-integer formulation: digits of c2 as integers, key
+    polynomials reconstructed by CRT over q_0 .. q_{l-1}, P, exact negacyclic
+    products over the integers, exact rounding of the sum divided by P."""
+    import workloads
+    mods = workloads.moduli("uneven")[:3]        # q0, q1 and the special prime P
+    l, n = 2, 8
+    P = mods[-1]
+    QP = mods[0] * mods[1] * P
+    rng = np.random.default_rng(21)
+    c = np.stack([np.stack([rng.integers(0, mods[i], size=n, dtype=np.uint64) for i in range(l)])
+                  for _ in range(3)])[None]                                   # [1][3][l][n], NTT domain
+    ksk = np.stack([np.stack([np.stack([rng.integers(0, mods[t], size=n, dtype=np.uint64) for t in range(l + 1)])
+                              for _ in range(2)]) for _ in range(l)])        # [l][2][l+1][n]
+    got = oracle.batch_ntt(oracle.relin(c, ksk, mods)[0], mods[:l], -1)       # [2][l][n], coefficients
+    cc = oracle.batch_ntt(c[0], mods[:l], -1)                                # [3][l][n]
+    kc = oracle.batch_ntt(ksk.reshape(l * 2, l + 1, n), mods, -1).reshape(l, 2, l + 1, n)
+
+    def crt(res):
+        x = 0
+        for r, q in zip(res, mods):
+            Mi = QP // q
+            x += int(r) * Mi * pow(Mi, -1, q)
+        return x % QP
+
+    def negacyclic(a, b):
+        out = [0] * n
+        for i in range(n):
+            for j in range(n):
+                if i + j < n:
+                    out[i + j] += a[i] * b[j]
+                else:
+                    out[i + j - n] -= a[i] * b[j]
+        return out
+
+    for s in range(2):
+        S = [0] * n
+        for j in range(l):
+            digit = [int(v) for v in cc[2, j]]                               # [c2]_{q_j} as integers
+            key = [crt(kc[j, s, :, k]) for k in range(n)]
+            S = [x + y for x, y in zip(S, negacyclic(digit, key))]
+        for k in range(n):
+            X = S[k] % QP
+            r = (X + (P - 1) // 2) // P
+            for i in range(l):
+                assert int(got[s, i, k]) == (int(cc[s, i, k]) + r) % mods[i], (s, i, k)
