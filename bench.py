@@ -32,7 +32,7 @@ def parse():
                     help="untimed steps; the clocks settle after about 20 steps of the default workload")
     ap.add_argument("--workload", default="ckks_level",
                     choices=["ckks_level", "ct_tensor", "plain4096", "uneven", "serving", "ladder", "rescale",
-                             "matmul"])
+                             "matmul", "routines"])
     ap.add_argument("--requests", type=int, default=2200, help="serving: requests per trace (first 200 warm up)")
     ap.add_argument("--grid", type=int, default=0, help="persistent workgroups for the uneven batch (0 = tuned/default)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -456,6 +456,75 @@ def bench_matmul(args):
     print(json.dumps(result), flush=True)
 
 
+def bench_routines(args):
+    """The paper's HE routine benchmark (section IV-C) on its parameters,
+    N = 2^15 and 8 primes (plus a special prime for the key switch), NTT
+    domain, synthetic ciphertexts and key: MulLin = Mul (tensor) + Relin;
+    MulLinRS = MulLin + rescale.  One ciphertext pair (the paper's unbatched
+    routines) and a batch of 32.  Value: MulLinRS per second at batch 32."""
+    import torch
+    import workloads
+    import paper_2109_14704_amd as H
+    chain = workloads.moduli("ct_tensor")
+    l, logn = 8, 15
+    n_ = 1 << logn
+    t8, t9 = H.Tables(logn, chain[:l]), H.Tables(logn, chain[:l + 1])
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(2109_14704 + 9)
+
+    def operand(shape, mods):
+        x = torch.empty(shape + (len(mods), n_), dtype=torch.int64, device="cuda:0")
+        for i, q in enumerate(mods):
+            x[..., i, :].copy_(torch.randint(0, q, shape + (n_,), generator=gen, device="cuda:0", dtype=torch.int64))
+        return x
+
+    ksk = operand((l, 2), chain[:l + 1])
+    rows = []
+    for batch in (1, 32):
+        c, d = operand((batch, 2), chain[:l]), operand((batch, 2), chain[:l])
+        prod = torch.empty((batch, 3, l, n_), dtype=torch.int64, device="cuda:0")
+        lin = torch.empty((batch, 2, l, n_), dtype=torch.int64, device="cuda:0")
+        rs = torch.empty((batch * 2, l - 1, n_), dtype=torch.int64, device="cuda:0")
+
+        def mullin():
+            H.ct_tensor(t8, c, d, out=prod, in_ntt=True, out_ntt=True)
+            H.relin(t9, prod, ksk, out=lin)
+
+        def mullinrs():
+            mullin()
+            H.rescale(t8, lin.view(batch * 2, l, n_), out=rs, ntt=True)
+
+        for name, fn in (("MulLin", mullin), ("MulLinRS", mullinrs)):
+            for _ in range(max(3, args.warmup // 2)):
+                fn()
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = max(5, args.steps)
+            a.record()
+            for _ in range(reps):
+                fn()
+            b.record()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / reps
+            rows.append({"routine": name, "batch": batch, "us": round(ms * 1e3, 1),
+                         "per_s": round(batch / ms * 1e3, 1)})
+    H.prof_enable(True)
+    for _ in range(3):
+        mullinrs()
+    torch.cuda.synchronize()
+    prof = H.prof_read()
+    H.prof_enable(False)
+    value = [r for r in rows if r["routine"] == "MulLinRS" and r["batch"] == 32][0]
+    info = {"workload": "routines", "N": n_, "limbs": l, "special_primes": 1, "batches": [1, 32],
+            "ops": "MulLin = tensor + relin; MulLinRS = MulLin + rescale (NTT domain)"}
+    result = {"metric": METRIC, "value": value["per_s"], "unit": "MulLinRS/s", "n_gpus": 1,
+              "steps": max(5, args.steps), "warmup": max(3, args.warmup // 2), "ms_per_step": value["us"] / 1e3,
+              "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+              "data": "synthetic", "config": info, "roofline": None,
+              "kernels_ms": {k: round(v[0] / v[1], 4) for k, v in sorted(prof.items())}, "routines": rows}
+    print(json.dumps(result), flush=True)
+
+
 def bench_serving(args):
     """Poisson ct-mul serving: saturation throughput, then p50/p99 latency of the
     continuous-batching server and of per-request launches on the same traces
@@ -524,6 +593,11 @@ def bench_serving(args):
 
 def main():
     args = parse()
+    if args.workload == "routines":
+        if args.gpus != 1:
+            print("bench.py: one GPU only", file=sys.stderr)
+            sys.exit(2)
+        return bench_routines(args)
     if args.workload == "matmul":
         if args.gpus != 1:
             print("bench.py: one GPU only", file=sys.stderr)

@@ -122,6 +122,17 @@ int hentt_rescale(const hentt_tables *t, const uint64_t *c, uint64_t *out, uint3
 int hentt_ct_matmul(const hentt_tables *t, const uint64_t *A, const uint64_t *B, uint64_t *C, uint32_t m, uint32_t n,
                     uint32_t k, void *stream);
 
+/* Relinearization Relin of section II-A with the RNS digit key switch:
+ * c' = (c0, c1) + round(P^-1 sum_j [c2]_{q_j} evk_j) mod q, NTT domain in and
+ * out.  t holds l + 1 limbs: the ciphertext's primes q_0 .. q_{l-1} followed
+ * by the special prime P (l >= 1).  c [batch][3][l][N] (the Mul tensor),
+ * ksk [l][2][l + 1][N] (digit j, component s, prime: the key-switching key,
+ * caller-owned), out [batch][2][l][N]; canonical inputs and outputs.  out must
+ * not overlap c or ksk (HENTT_EINVAL).  The last limb's rescale constants are
+ * made on the first call (a synchronous upload); later calls only enqueue. */
+int hentt_relin(const hentt_tables *t, const uint64_t *c, const uint64_t *ksk, uint64_t *out, uint32_t batch,
+                void *stream);
+
 /* Kernel-design ladder of the forward transform (section III-B and the
  * NTT evaluation of section IV): the same result as hentt_ntt_fwd, computed
  * by reference kernel designs so that they can be timed against each other.

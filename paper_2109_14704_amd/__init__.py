@@ -13,7 +13,7 @@ import torch
 
 __all__ = ["HenttError", "Tables", "ntt_fwd", "ntt_inv", "dyadic_mul", "polymul", "ct_tensor", "ntt_batch",
            "psi", "lib", "LIB_PATH", "prof_enable", "prof_read", "BatchPlan", "stage_split", "ntt_fwd_variant",
-           "rescale", "ct_matmul"]
+           "rescale", "ct_matmul", "relin"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("HENTT_LIB") or os.path.join(_HERE, "libhentt.so")  # HENTT_LIB: alternative build
@@ -54,6 +54,7 @@ def lib():
             "hentt_ntt_fwd_variant": [_VP, _VP, _U32, ctypes.c_int, _VP],
             "hentt_rescale": [_VP, _VP, _VP, _U32, _U32, _VP],
             "hentt_ct_matmul": [_VP, _VP, _VP, _VP, _U32, _U32, _U32, _VP],
+            "hentt_relin": [_VP, _VP, _VP, _VP, _U32, _VP],
             "hentt_ntt_inv": [_VP, _VP, _U32, _VP],
             "hentt_dyadic_mul": [_VP, _VP, _VP, _VP, _U32, _VP],
             "hentt_polymul": [_VP, _VP, _VP, _VP, _U32, _VP],
@@ -238,6 +239,25 @@ def ct_matmul(tables, A, B, C, stream=None):
     _check(lib().hentt_ct_matmul(tables.handle, _words(A, "A"), _words(B, "B"), _words(C, "C"), m, n, k,
                                  _stream(stream)), "hentt_ct_matmul")
     return C
+
+
+def relin(tables, c, ksk, out=None, stream=None):
+    """Relinearization (section II-A) with the RNS digit key switch, NTT domain.
+    tables: l + 1 limbs, the ciphertext's primes then the special prime P;
+    c [batch, 3, l, N]; ksk [l, 2, l + 1, N] -> out [batch, 2, l, N]."""
+    l, n_ = tables.limbs - 1, tables.n
+    if c.dim() != 4 or c.shape[1:] != (3, l, n_):
+        raise HenttError("c must have shape [batch, 3, %d, %d]" % (l, n_))
+    if tuple(ksk.shape) != (l, 2, l + 1, n_):
+        raise HenttError("ksk must have shape [%d, 2, %d, %d]" % (l, l + 1, n_))
+    batch = c.shape[0]
+    if out is None:
+        out = torch.empty((batch, 2, l, n_), dtype=c.dtype, device=c.device)
+    elif tuple(out.shape) != (batch, 2, l, n_):
+        raise HenttError("out must have shape [%d, 2, %d, %d]" % (batch, l, n_))
+    _check(lib().hentt_relin(tables.handle, _words(c, "c"), _words(ksk, "ksk"), _words(out, "out"), batch,
+                             _stream(stream)), "hentt_relin")
+    return out
 
 
 # Kernel designs of hentt_ntt_fwd_variant (the ladder of section III-B).

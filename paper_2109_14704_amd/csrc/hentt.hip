@@ -16,6 +16,7 @@
 #include "ntt_kernels.hpp"
 #include "batch_kernels.hpp"
 #include "rescale_kernels.hpp"
+#include "keyswitch_kernels.hpp"
 
 using namespace hentt;
 
@@ -116,6 +117,7 @@ struct Storage {
   int device = 0;
   std::mutex rs_mu;            // rescale constants per level (limb count), made on first use
   std::map<uint32_t, RsLimb *> rs;
+  uint64_t *d_mu = nullptr;    // [limbs] floor(2^64 / q), made on first use (key switching)
 };
 
 void release(Storage *s) {
@@ -126,6 +128,7 @@ void release(Storage *s) {
     if (s->d_tw) (void)hipFree(s->d_tw);
     if (s->d_lc) (void)hipFree(s->d_lc);
     for (auto &kv : s->rs) (void)hipFree(kv.second);
+    if (s->d_mu) (void)hipFree(s->d_mu);
     (void)hipSetDevice(cur);
     delete s;
   }
@@ -243,8 +246,9 @@ namespace {
 // takes 5 stages at N = 2^15 and 2^16, leaving 2^10 / 2^11 blocks to the
 // ALU-bound block and fused kernels (the 5-stage split was 10% faster on the
 // CKKS-level batch and 19% on the ciphertext tensor than 3 / 4 stages).
+constexpr uint32_t kWholeMaxLogN = 14;  // largest transform done whole by one workgroup
 template <int LOGN> struct Plan {
-  static constexpr bool WHOLE = LOGN <= 14;
+  static constexpr bool WHOLE = LOGN <= (int)kWholeMaxLogN;
   static constexpr int EC = LOGN == 15 ? HENTT_EC15 : LOGN == 16 ? HENTT_EC16 : LOGN == 17 ? 4 : (LOGN > 12 ? LOGN - 12 : 1);
   static constexpr int B = LOGN - EC;
   // fused products: one kernel up to 2^12, else a column pass of PEC stages
@@ -650,6 +654,100 @@ int run_rescale(const hentt_tables *t, const uint64_t *c, uint64_t *out, uint32_
   return HENTT_OK;
 }
 
+// ------------------------------------------------------- relinearization
+int ks_mu(Storage *s, const uint64_t **out) {
+  std::lock_guard<std::mutex> lk(s->rs_mu);
+  if (!s->d_mu) {
+    std::vector<uint64_t> mu(s->limbs);
+    for (uint32_t t = 0; t < s->limbs; ++t) mu[t] = (uint64_t)(((u128)1 << 64) / s->moduli[t]);
+    uint64_t *d = nullptr;
+    hipError_t e = hipMalloc(&d, s->limbs * sizeof(uint64_t));
+    if (e == hipSuccess) e = hipMemcpy(d, mu.data(), s->limbs * sizeof(uint64_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      if (d) (void)hipFree(d);
+      return hip_fail(e);
+    }
+    s->d_mu = d;
+  }
+  *out = s->d_mu;
+  return HENTT_OK;
+}
+
+// Key-switch split: the digit loop holds two accumulator arrays, so whole
+// transforms only up to 2^12 (256 lanes); above, a column pass of EC stages
+// and blocks of at most 2^12.
+template <int LOGN> struct KsPlan {
+  static constexpr bool WHOLE = LOGN <= 12;
+  static constexpr int EC = LOGN <= 12 ? 0 : (LOGN == 15 || LOGN == 16 || LOGN == 17) ? 5 : LOGN - 12;
+  static constexpr int B = LOGN - EC;
+};
+
+template <int LOGN> void launch_keyswitch(const KsArgs &a, const Storage *s, hipStream_t st) {
+  const uint32_t L1 = a.l + 1;
+  using P = KsPlan<LOGN>;
+  if constexpr (P::WHOLE) {
+    LaunchTimer lt_("k_ks_whole", LOGN, st);
+    hipLaunchKernelGGL((k_ks_whole<LOGN, 4>), dim3(a.batch * L1), dim3(1 << (LOGN - 4)), 0, st, a, s->d_tw, s->d_lc);
+  } else {
+    {
+      LaunchTimer lt_("k_ks_cols", LOGN, st);
+      hipLaunchKernelGGL((k_ks_cols<LOGN, P::EC>), dim3(a.batch * a.l * L1 * ((1u << (LOGN - P::EC)) / 256)),
+                         dim3(256), 0, st, a, s->d_tw, s->d_lc);
+    }
+    LaunchTimer lt_("k_ks_blocks", LOGN, st);
+    hipLaunchKernelGGL((k_ks_blocks<LOGN, P::B, 4>), dim3((a.batch * L1) << (LOGN - P::B)), dim3(1 << (P::B - 4)), 0,
+                       st, a, s->d_tw, s->d_lc);
+  }
+}
+typedef void (*ks_fn)(const KsArgs &, const Storage *, hipStream_t);
+#define KS_ENTRY(n) launch_keyswitch<n>,
+const ks_fn k_ks_table[] = {HENTT_SIZES(KS_ENTRY)};
+
+int run_relin(const hentt_tables *t, const uint64_t *c, const uint64_t *ksk, uint64_t *out, uint32_t batch,
+              hipStream_t st) {
+  Storage *s = t->s;
+  const uint32_t ln = s->log_n, L1 = t->limbs, l = L1 - 1;
+  const uint64_t N = 1ull << ln, P = (uint64_t)l * N;
+  const uint64_t *mu = nullptr;
+  int rc = ks_mu(s, &mu);
+  if (rc) return rc;
+  const bool two_pass = ln > 12;  // KsPlan<>::WHOLE
+  const size_t d_bytes = (size_t)batch * P * 8, acc_bytes = (size_t)batch * 2 * L1 * N * 8;
+  const size_t e_bytes = two_pass ? (size_t)batch * l * L1 * N * 8 : 0;
+  void *buf = nullptr;
+  rc = pool_get(d_bytes + acc_bytes + e_bytes, st, &buf);
+  if (rc) return rc;
+  uint64_t *d = (uint64_t *)buf, *acc = d + batch * P, *e = acc + (size_t)batch * 2 * L1 * N;
+  // digits: c2 in the coefficient domain, modulo its own primes
+  hipError_t he = hipMemcpy2DAsync(d, P * 8, c + 2 * P, 3 * P * 8, P * 8, batch, hipMemcpyDeviceToDevice, st);
+  const hentt_tables lv{s, l};
+  if (he == hipSuccess) rc = run_transform(&lv, d, batch, st, true);
+  if (he == hipSuccess && !rc) {
+    KsArgs a{};
+    a.d = d;
+    a.ksk = ksk;
+    a.e = two_pass ? e : nullptr;
+    a.acc = acc;
+    a.mu = mu;
+    a.batch = batch;
+    a.l = l;
+    k_ks_table[ln - HENTT_LOG_N_MIN](a, s, st);
+    he = hipGetLastError();
+    // divide by P with rounding, over q_0 .. q_{l-1}: [batch][2][l+1] -> [batch][2][l]
+    if (he == hipSuccess) rc = run_rescale(t, acc, out, batch * 2, true, st);
+    if (he == hipSuccess && !rc) {
+      const uint32_t tiles = (uint32_t)((N + 2047) / 2048);
+      LaunchTimer lt_("k_ks_add", (int)ln, st);
+      hipLaunchKernelGGL(k_ks_add, dim3(batch * 2 * l * tiles), dim3(256), 0, st, c, out, s->d_lc, l, ln, tiles);
+      he = hipGetLastError();
+    }
+  }
+  pool_put(buf);
+  if (rc) return rc;
+  if (he != hipSuccess) return hip_fail(he);
+  return HENTT_OK;
+}
+
 int run_prod(const hentt_tables *t, int mode, const ProdArgs &pa, uint32_t batch, bool in_coeff, bool out_coeff,
              hipStream_t st) {
   const int ln = (int)t->s->log_n;
@@ -877,6 +975,17 @@ int hentt_ct_matmul(const hentt_tables *t, const uint64_t *A, const uint64_t *B,
                      t->s->log_n, tiles);
   HIPCHK(hipGetLastError());
   return HENTT_OK;
+}
+
+int hentt_relin(const hentt_tables *t, const uint64_t *c, const uint64_t *ksk, uint64_t *out, uint32_t batch,
+                void *stream) {
+  if (!t || !c || !ksk || !out || batch == 0 || t->limbs < 2) return HENTT_EINVAL;
+  const uint64_t N = 1ull << t->s->log_n, l = t->limbs - 1;
+  const uintptr_t o0 = (uintptr_t)out, o1 = o0 + (uintptr_t)(batch * 2 * l * N * 8);
+  const uintptr_t c0 = (uintptr_t)c, c1 = c0 + (uintptr_t)(batch * 3 * l * N * 8);
+  const uintptr_t k0 = (uintptr_t)ksk, k1 = k0 + (uintptr_t)(l * 2 * (l + 1) * N * 8);
+  if ((o0 < c1 && c0 < o1) || (o0 < k1 && k0 < o1)) return HENTT_EINVAL;  // out overlaps an input
+  return run_relin(t, c, ksk, out, batch, (hipStream_t)stream);
 }
 
 int hentt_ntt_inv(const hentt_tables *t, uint64_t *x, uint32_t batch, void *stream) {

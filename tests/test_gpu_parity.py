@@ -214,6 +214,23 @@ def test_ct_matmul_paper_shape_sampled(gpu):
         assert np.array_equal(host(Cd[i:i + 1, j:j + 1]), want), (i, j)
 
 
+@pytest.mark.parametrize("log_n,l", [(6, 2), (12, 3), (13, 2), (14, 3), (15, 2), (16, 2), (17, 2), (12, 1)])
+def test_relin(gpu, log_n, l):
+    """Relinearization (digit key switch, division by the special prime with
+    rounding), element by element against the oracle."""
+    import paper_2109_14704_amd as H
+    print("case relin log_n=%d l=%d" % (log_n, l), flush=True)
+    mods = CHAIN[:l + 1]                     # the last one plays the special prime P
+    rng = np.random.default_rng(700 + 7 * log_n + l)
+    c = rand_limbs(rng, (2, 3, l, 1 << log_n), mods[:l])
+    ksk = rand_limbs(rng, (l, 2, l + 1, 1 << log_n), mods)
+    t = H.Tables(log_n, mods)
+    cd = dev(c, gpu)
+    got = H.relin(t, cd, dev(ksk, gpu))
+    assert np.array_equal(host(got), oracle.relin(c, ksk, mods))
+    assert np.array_equal(host(cd), c)
+
+
 def test_plain4096_workload(gpu):
     """Workload 1 at full size: 8 polys fwd + inv, one polymul vs schoolbook."""
     import paper_2109_14704_amd as H
