@@ -246,8 +246,8 @@ def cpu_baseline(s, target_s):
 # multiplier; v_mad_u64_u32 / v_mul_hi_u32 / v_mul_lo_u32 issue at full rate, so
 # every VALU op costs one issue slot):
 VALU_BFLY = 21     # Harvey/Shoup butterfly: 9 32-bit multiplies + 12 adds, compares, selects
-VALU_PROD = 38     # Barrett product a*b mod q: 128-bit product, quotient estimate, 3 corrections
-VALU_TENSOR = 121  # c0d0, c1d1 (2 x 38) + c0d1 + c1d0 with one reduction (45)
+VALU_PROD = 19     # Montgomery product a b R^-1 mod q: 128-bit product, low product by -q^-1, high product by q
+VALU_TENSOR = 68   # c0d0, c1d1 (2 x 19) + c0d1 + c1d0 with one Montgomery reduction (30)
 VALU_RS_EPI = 17   # rescale epilogue: Shoup product by qL^-1 (9 + adds) and a reduction from [0, 4q)
 VALU_MAC = 121     # one matMul product term: the tensor's three outputs accumulated with mad_mod
 

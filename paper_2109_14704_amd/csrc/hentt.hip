@@ -113,6 +113,8 @@ struct Storage {
   uint32_t log_n = 0, limbs = 0;
   Tw *d_tw = nullptr;          // [limbs][2][N]
   LimbConst *d_lc = nullptr;   // [limbs]
+  LimbConst *d_lcm = nullptr;  // [limbs] the same with N^-1 R mod q for N^-1 (after Montgomery products)
+  uint64_t *d_qinv = nullptr;  // [limbs] -q^-1 mod 2^64
   std::vector<uint64_t> moduli;
   int device = 0;
   std::mutex rs_mu;            // rescale constants per level (limb count), made on first use
@@ -127,6 +129,8 @@ void release(Storage *s) {
     (void)hipSetDevice(s->device);
     if (s->d_tw) (void)hipFree(s->d_tw);
     if (s->d_lc) (void)hipFree(s->d_lc);
+    if (s->d_lcm) (void)hipFree(s->d_lcm);
+    if (s->d_qinv) (void)hipFree(s->d_qinv);
     for (auto &kv : s->rs) (void)hipFree(kv.second);
     if (s->d_mu) (void)hipFree(s->d_mu);
     (void)hipSetDevice(cur);
@@ -322,7 +326,10 @@ template <int LOGN, int MODE>
 void launch_prod(const hentt_tables *t, const ProdArgs &pa, uint32_t batch, bool in_coeff, bool out_coeff,
                  uint64_t *ws, hipStream_t st) {
   const Tw *tw = t->s->d_tw;
-  const LimbConst *lc = t->s->d_lc;
+  // outputs going back to the coefficient domain take Montgomery products,
+  // whose R^-1 the inverse transform's folded N^-1 R scaling cancels
+  const LimbConst *lc = out_coeff ? t->s->d_lcm : t->s->d_lc;
+  const uint64_t *qinv = t->s->d_qinv;
   const uint32_t L = t->limbs;
   const uint32_t units = batch * L;
   constexpr int NIN = ProdShape<MODE>::NIN, NOUT = ProdShape<MODE>::NOUT;
@@ -335,9 +342,9 @@ void launch_prod(const hentt_tables *t, const ProdArgs &pa, uint32_t batch, bool
   constexpr int PE = ProdE<MODE>::E;
   if constexpr (P::PROD_WHOLE) {
     const dim3 g(units), blk(1 << (LOGN - PE));
-    if (in_coeff && out_coeff) { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, LOGN, PE, MODE, true, true>), g, blk, prod_lds_pad(), st, pa, tw, lc, batch, L); }
-    else if (in_coeff) { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, LOGN, PE, MODE, true, false>), g, blk, prod_lds_pad(), st, pa, tw, lc, batch, L); }
-    else { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, LOGN, PE, MODE, false, true>), g, blk, prod_lds_pad(), st, pa, tw, lc, batch, L); }
+    if (in_coeff && out_coeff) { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, LOGN, PE, MODE, true, true>), g, blk, prod_lds_pad(), st, pa, tw, lc, qinv, batch, L); }
+    else if (in_coeff) { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, LOGN, PE, MODE, true, false>), g, blk, prod_lds_pad(), st, pa, tw, lc, qinv, batch, L); }
+    else { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, LOGN, PE, MODE, false, true>), g, blk, prod_lds_pad(), st, pa, tw, lc, qinv, batch, L); }
   } else {
     constexpr int EC = P::PEC, B = LOGN - P::PEC;
     const uint64_t NL = (uint64_t)L << LOGN;
@@ -357,9 +364,9 @@ void launch_prod(const hentt_tables *t, const ProdArgs &pa, uint32_t batch, bool
                          ca, tw, lc, batch, L); }
     }
     const dim3 g(units << (LOGN - B)), blk(1 << (B - PE));
-    if (in_coeff && out_coeff) { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, B, PE, MODE, true, true>), g, blk, prod_lds_pad(), st, pb, tw, lc, batch, L); }
-    else if (in_coeff) { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, B, PE, MODE, true, false>), g, blk, prod_lds_pad(), st, pb, tw, lc, batch, L); }
-    else { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, B, PE, MODE, false, true>), g, blk, prod_lds_pad(), st, pb, tw, lc, batch, L); }
+    if (in_coeff && out_coeff) { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, B, PE, MODE, true, true>), g, blk, prod_lds_pad(), st, pb, tw, lc, qinv, batch, L); }
+    else if (in_coeff) { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, B, PE, MODE, true, false>), g, blk, prod_lds_pad(), st, pb, tw, lc, qinv, batch, L); }
+    else { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, B, PE, MODE, false, true>), g, blk, prod_lds_pad(), st, pb, tw, lc, qinv, batch, L); }
     if (out_coeff) {
       ColArgs ca{};
       for (int o = 0; o < NOUT; ++o) ca.src[o] = ca.dst[o] = pa.out[o];
@@ -639,6 +646,8 @@ int run_rescale(const hentt_tables *t, const uint64_t *c, uint64_t *out, uint32_
     last.limbs = 1;
     last.d_tw = s->d_tw + (size_t)L * 2 * N;
     last.d_lc = s->d_lc + L;
+    last.d_lcm = s->d_lcm + L;
+    last.d_qinv = s->d_qinv + L;
     last.device = s->device;
     const hentt_tables lv{&last, 1};
     rc = run_transform(&lv, (uint64_t *)tl, batch, st, true);
@@ -842,7 +851,8 @@ int hentt_tables_create(uint32_t log_n, uint32_t limbs, const uint64_t *moduli_h
   }
   const uint32_t N = 1u << log_n;
   std::vector<Tw> tw((size_t)limbs * 2 * N);
-  std::vector<LimbConst> lc(limbs);
+  std::vector<LimbConst> lc(limbs), lcm(limbs);
+  std::vector<uint64_t> qinv(limbs);
   std::vector<uint64_t> pw(N), ipw(N);
   for (uint32_t l = 0; l < limbs; ++l) {
     const uint64_t q = moduli_host[l];
@@ -874,6 +884,16 @@ int hentt_tables_create(uint32_t log_n, uint32_t limbs, const uint64_t *moduli_h
     c.ninvw_s = shoup_quot(c.ninvw, q);
     c.k = (uint32_t)bit_length(q);
     c.mu = (uint64_t)(((u128)1 << (2 * c.k)) / q);
+    uint64_t qi = q;  // q^-1 mod 2^64 by Newton's iteration (3 -> 96 bits)
+    for (int i = 0; i < 5; ++i) qi *= 2 - q * qi;
+    qinv[l] = 0 - qi;
+    const uint64_t r = (uint64_t)(((u128)1 << 64) % q);
+    LimbConst &cm = lcm[l];
+    cm = c;
+    cm.ninv = h_mul(c.ninv, r, q);
+    cm.ninv_s = shoup_quot(cm.ninv, q);
+    cm.ninvw = h_mul(c.ninvw, r, q);
+    cm.ninvw_s = shoup_quot(cm.ninvw, q);
   }
   Storage *s = new (std::nothrow) Storage();
   if (!s) return HENTT_ENOMEM;
@@ -885,8 +905,14 @@ int hentt_tables_create(uint32_t log_n, uint32_t limbs, const uint64_t *moduli_h
   hipError_t e = hipMalloc(&s->d_tw, tw.size() * sizeof(Tw));
   if (e == hipSuccess) e = hipMalloc(&s->d_lc, lc.size() * sizeof(LimbConst));
   if (e == hipSuccess) e = hipMemcpyAsync(s->d_tw, tw.data(), tw.size() * sizeof(Tw), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMalloc(&s->d_lcm, lcm.size() * sizeof(LimbConst));
+  if (e == hipSuccess) e = hipMalloc(&s->d_qinv, qinv.size() * sizeof(uint64_t));
   if (e == hipSuccess)
     e = hipMemcpyAsync(s->d_lc, lc.data(), lc.size() * sizeof(LimbConst), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s->d_lcm, lcm.data(), lcm.size() * sizeof(LimbConst), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(s->d_qinv, qinv.data(), qinv.size() * sizeof(uint64_t), hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) {
     release(s);

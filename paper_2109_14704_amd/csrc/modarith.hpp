@@ -153,4 +153,33 @@ __device__ __forceinline__ uint64_t mac2mod(uint64_t a, uint64_t b, uint64_t c, 
   return barrett(h + (s < l ? 1 : 0), s, q, mu, k);
 }
 
+// Montgomery reduction (Montgomery 1985) with R = 2^64, for the products
+// whose factor R^-1 is cancelled elsewhere (folded into the N^-1 scaling of
+// the inverse transform that follows them).  For T = hi 2^64 + lo < q R and
+// qinv = -q^-1 mod 2^64, m = lo qinv mod 2^64 makes T + m q a multiple of R;
+// its low word is zero, with a carry out exactly when lo != 0, so
+// (T + m q) / R = hi + floor(m q / 2^64) + [lo != 0], which is T R^-1 mod q
+// in [0, 2q).  Two half products (a low one, a high one) and no correction
+// steps, where Barrett takes a full 128-bit product, a low product, two
+// variable shifts and three conditional subtractions.
+__device__ __forceinline__ uint64_t redc(uint64_t hi, uint64_t lo, uint64_t q, uint64_t qinv) {
+  const uint64_t m = lo * qinv;
+  return hi + mulhi64(m, q) + (lo != 0 ? 1 : 0);
+}
+// a b R^-1 mod q in [0, 2q) for a b < q R.
+__device__ __forceinline__ uint64_t mont_mul(uint64_t a, uint64_t b, uint64_t q, uint64_t qinv) {
+  uint64_t h, l;
+  mul128(a, b, h, l);
+  return redc(h, l, q, qinv);
+}
+// (a b + c d) R^-1 mod q in [0, 2q) for a b + c d < q R (one reduction).
+__device__ __forceinline__ uint64_t mont_mad(uint64_t a, uint64_t b, uint64_t c, uint64_t d, uint64_t q,
+                                            uint64_t qinv) {
+  uint64_t h1, l1, h2, l2;
+  mul128(a, b, h1, l1);
+  mul128(c, d, h2, l2);
+  const uint64_t l = l1 + l2;
+  return redc(h1 + h2 + (l < l1 ? 1 : 0), l, q, qinv);
+}
+
 }  // namespace hentt

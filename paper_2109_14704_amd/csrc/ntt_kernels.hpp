@@ -478,6 +478,37 @@ __device__ __forceinline__ void products(uint64_t (&X)[ProdShape<MODE>::NIN][1 <
   }
 }
 
+// The products ahead of an inverse transform, in Montgomery form: every
+// output is off by R^-1 (R = 2^64), a constant factor the inverse transform
+// removes with its N^-1 scaling, taken from the folded constants N^-1 R.
+// Inputs: MUL factors below 4q (a b < 16 q^2 < q R as q < 2^60); TENSOR
+// factors below 2q (c0 d1 + c1 d0 < 8 q^2 < q R).  Outputs in [0, 2q), a valid
+// inverse-transform input.
+template <int MODE, int E>
+__device__ __forceinline__ void products_mont(uint64_t (&X)[ProdShape<MODE>::NIN][1 << E],
+                                              uint64_t (&Y)[ProdShape<MODE>::NOUT][1 << E], uint64_t q,
+                                              uint64_t qinv) {
+#pragma unroll
+  for (int s = 0; s < (1 << E); ++s) {
+    if constexpr (MODE == PROD_MUL) {
+      Y[0][s] = mont_mul(X[0][s], X[1][s], q, qinv);
+    } else {
+      Y[0][s] = mont_mul(X[0][s], X[2][s], q, qinv);
+      Y[1][s] = mont_mad(X[0][s], X[3][s], X[1][s], X[2][s], q, qinv);
+      Y[2][s] = mont_mul(X[1][s], X[3][s], q, qinv);
+    }
+  }
+}
+
+// Forward outputs ([0, 8q)) brought to the factor range of products_mont.
+template <int MODE, int E> __device__ __forceinline__ void reduce_for_mont(uint64_t (&x)[1 << E], const ModQ &m) {
+#pragma unroll
+  for (int s = 0; s < (1 << E); ++s) {
+    x[s] = csubn(x[s], m.nq4);
+    if constexpr (MODE == PROD_TENSOR) x[s] = csubn(x[s], m.nq2);
+  }
+}
+
 // One workgroup per block of 2^B coefficients of one (batch entry, limb):
 // forward block rounds of every input (DO_FWD; otherwise the inputs are
 // already NTT-domain values), the products in registers, then the inverse
@@ -486,10 +517,15 @@ __device__ __forceinline__ void products(uint64_t (&X)[ProdShape<MODE>::NIN][1 <
 // values, so the product needs no data exchange and the NTT-domain values
 // never leave the chip.  With B == LOGN the whole product is one kernel;
 // with B < LOGN the forward column pass runs before it and the inverse
-// column pass after it.
+// column pass after it.  With DO_INV the products are Montgomery products
+// and lc must hold the folded constants (N^-1 R in place of N^-1), also for
+// the inverse column pass that completes the transform; qinv[limb] is
+// -q^-1 mod 2^64.  Without DO_INV the products are exact (Barrett) and lc
+// the plain constants.
 template <int LOGN, int B, int E, int MODE, bool DO_FWD, bool DO_INV>
 __global__ __launch_bounds__(1 << (B - E)) void k_prod(ProdArgs a, const Tw *__restrict__ tw,
-                                                        const LimbConst *__restrict__ lc, uint32_t batch,
+                                                        const LimbConst *__restrict__ lc,
+                                                        const uint64_t *__restrict__ qinv, uint32_t batch,
                                                         uint32_t limbs) {
   constexpr int NIN = ProdShape<MODE>::NIN, NOUT = ProdShape<MODE>::NOUT;
   __shared__ uint64_t lds[(DO_FWD || DO_INV) ? LdsSize<B>::value : 2];
@@ -522,7 +558,8 @@ __global__ __launch_bounds__(1 << (B - E)) void k_prod(ProdArgs a, const Tw *__r
       const Tw *tp = opaque(t);
       load_global<B, E, F::LO, F::R, true>(v, a.in[p] + in_off, RoundMap<B, E, F::LO, F::R>::lane_part(tid));
       fwd_block_rounds<B, E, F::LO, F::R>(v, LOGN, lds, tid, blockStart, tp, c.m);
-      reduce_fwd<E>(v, c.m);
+      if constexpr (DO_INV) reduce_for_mont<MODE, E>(v, c.m);
+      else reduce_fwd<E>(v, c.m);
     } else {
       load_global<B, E, 0, E, true>(v, a.in[p] + in_off, M0::lane_part(tid));
     }
@@ -537,7 +574,8 @@ __global__ __launch_bounds__(1 << (B - E)) void k_prod(ProdArgs a, const Tw *__r
     });
   }
   uint64_t Y[NOUT][1 << E];
-  products<MODE, E>(X, Y, c);
+  if constexpr (DO_INV) products_mont<MODE, E>(X, Y, c.m.q, qinv[limb]);
+  else products<MODE, E>(X, Y, c);
 #pragma unroll 1
   for (int o = 0; o < NOUT; ++o) {
     uint64_t v[1 << E];

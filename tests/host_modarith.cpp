@@ -1,7 +1,8 @@
 // CPU property test of the device modular arithmetic (modarith.hpp built for
 // the host).  Checks Algorithm 1's contract (inputs and outputs in [0, 4q),
 // X' = X + W Y, Y' = X - W Y mod q), the inverse butterfly's [0, 2q) contract,
-// and the Barrett/Shoup/mad_mod products against exact 128-bit arithmetic.
+// the Barrett/Shoup/mad_mod products and the Montgomery reduction against
+// exact 128-bit arithmetic.
 #include <stdint.h>
 #include <stdio.h>
 #include <random>
@@ -69,6 +70,23 @@ int main(int argc, char **argv) {
     EXPECT(mulmod(u, v, q, mu, kk) == mm(u, v, q), "mulmod q=%llx\n", (unsigned long long)q);
     uint64_t want = (uint64_t)(((u128)u * v + (u128)s * t) % q);
     EXPECT(madmod(u, v, s, t, q, mu, kk) == want, "madmod q=%llx\n", (unsigned long long)q);
+    // Montgomery products, R = 2^64: x R == T (mod q) and x < 2q for T < q R,
+    // at the input ranges the fused product uses (one factor below 4q or 2q)
+    uint64_t qinv = q;  // q^-1 mod 2^64 by Newton's iteration (3 -> 96 bits)
+    for (int i = 0; i < 5; ++i) qinv *= 2 - q * qinv;
+    EXPECT(q * qinv == 1, "q^-1 mod 2^64\n");
+    qinv = 0 - qinv;
+    uint64_t a4 = (it % 9 == 0) ? 4 * q - 1 : g() % (4 * q), b4 = (it % 10 == 0) ? 4 * q - 1 : g() % (4 * q);
+    uint64_t x3 = mont_mul(a4, b4, q, qinv);
+    EXPECT(x3 < 2 * q && (((u128)x3 << 64) % q) == ((u128)a4 * b4) % q, "mont_mul q=%llx\n", (unsigned long long)q);
+    uint64_t c2 = (it % 11 == 0) ? 2 * q - 1 : g() % (2 * q), d2 = (it % 12 == 0) ? 2 * q - 1 : g() % (2 * q);
+    uint64_t a2 = a4 % (2 * q), b2 = b4 % (2 * q);
+    uint64_t x4 = mont_mad(a2, d2, c2, b2, q, qinv);
+    u128 T4 = (u128)a2 * d2 + (u128)c2 * b2;
+    EXPECT(x4 < 2 * q && (((u128)x4 << 64) % q) == T4 % q, "mont_mad q=%llx\n", (unsigned long long)q);
+    // the reduction itself at the edge T = q R - 1 and at T = 0
+    uint64_t x5 = redc(q - 1, ~0ull, q, qinv), x6 = redc(0, 0, q, qinv);
+    EXPECT(x5 < 2 * q && (((u128)x5 << 64) % q) == ((((u128)(q - 1)) << 64) | ~0ull) % q && x6 == 0, "redc edges\n");
   }
   printf(fails ? "FAIL %d\n" : "OK\n", fails);
   return fails ? 1 : 0;
