@@ -119,7 +119,7 @@ struct Storage {
   int device = 0;
   std::mutex rs_mu;            // rescale constants per level (limb count), made on first use
   std::map<uint32_t, RsLimb *> rs;
-  uint64_t *d_mu = nullptr;    // [limbs] floor(2^64 / q), made on first use (key switching)
+  std::map<uint32_t, KsLimb *> ks;  // key-switching constants per level (limb count), made on first use
 };
 
 void release(Storage *s) {
@@ -132,7 +132,7 @@ void release(Storage *s) {
     if (s->d_lcm) (void)hipFree(s->d_lcm);
     if (s->d_qinv) (void)hipFree(s->d_qinv);
     for (auto &kv : s->rs) (void)hipFree(kv.second);
-    if (s->d_mu) (void)hipFree(s->d_mu);
+    for (auto &kv : s->ks) (void)hipFree(kv.second);
     (void)hipSetDevice(cur);
     delete s;
   }
@@ -664,21 +664,36 @@ int run_rescale(const hentt_tables *t, const uint64_t *c, uint64_t *out, uint32_
 }
 
 // ------------------------------------------------------- relinearization
-int ks_mu(Storage *s, const uint64_t **out) {
+// Key-switching constants of the level with L1 limbs (the last one is P).
+int ks_consts(Storage *s, uint32_t L1, const KsLimb **out) {
   std::lock_guard<std::mutex> lk(s->rs_mu);
-  if (!s->d_mu) {
-    std::vector<uint64_t> mu(s->limbs);
-    for (uint32_t t = 0; t < s->limbs; ++t) mu[t] = (uint64_t)(((u128)1 << 64) / s->moduli[t]);
-    uint64_t *d = nullptr;
-    hipError_t e = hipMalloc(&d, s->limbs * sizeof(uint64_t));
-    if (e == hipSuccess) e = hipMemcpy(d, mu.data(), s->limbs * sizeof(uint64_t), hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-      if (d) (void)hipFree(d);
-      return hip_fail(e);
-    }
-    s->d_mu = d;
+  auto it = s->ks.find(L1);
+  if (it != s->ks.end()) {
+    *out = it->second;
+    return HENTT_OK;
   }
-  *out = s->d_mu;
+  const uint64_t P = s->moduli[L1 - 1];
+  std::vector<KsLimb> kc(L1);
+  for (uint32_t t = 0; t < L1; ++t) {
+    const uint64_t q = s->moduli[t];
+    uint64_t qi = q;  // q^-1 mod 2^64 by Newton's iteration
+    for (int i = 0; i < 5; ++i) qi *= 2 - q * qi;
+    kc[t].mu = (uint64_t)(((u128)1 << 64) / q);
+    kc[t].qinv = 0 - qi;
+    kc[t].r = (uint64_t)(((u128)1 << 64) % q);
+    kc[t].rs = shoup_quot(kc[t].r, q);
+    kc[t].pm = P % q;
+    kc[t].pms = shoup_quot(kc[t].pm, q);
+  }
+  KsLimb *d = nullptr;
+  hipError_t e = hipMalloc(&d, L1 * sizeof(KsLimb));
+  if (e == hipSuccess) e = hipMemcpy(d, kc.data(), L1 * sizeof(KsLimb), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    if (d) (void)hipFree(d);
+    return hip_fail(e);
+  }
+  s->ks[L1] = d;
+  *out = d;
   return HENTT_OK;
 }
 
@@ -689,6 +704,7 @@ template <int LOGN> struct KsPlan {
   static constexpr bool WHOLE = LOGN <= 12;
   static constexpr int EC = LOGN <= 12 ? 0 : (LOGN == 15 || LOGN == 16 || LOGN == 17) ? 5 : LOGN - 12;
   static constexpr int B = LOGN - EC;
+  static constexpr int E = 3;  // words per lane in the block kernel (3: occupancy over radix)
 };
 
 template <int LOGN> void launch_keyswitch(const KsArgs &a, const Storage *s, hipStream_t st) {
@@ -704,7 +720,7 @@ template <int LOGN> void launch_keyswitch(const KsArgs &a, const Storage *s, hip
                          dim3(256), 0, st, a, s->d_tw, s->d_lc);
     }
     LaunchTimer lt_("k_ks_blocks", LOGN, st);
-    hipLaunchKernelGGL((k_ks_blocks<LOGN, P::B, 4>), dim3((a.batch * L1) << (LOGN - P::B)), dim3(1 << (P::B - 4)), 0,
+    hipLaunchKernelGGL((k_ks_blocks<LOGN, P::B, P::E>), dim3((a.batch * L1) << (LOGN - P::B)), dim3(1 << (P::B - P::E)), 0,
                        st, a, s->d_tw, s->d_lc);
   }
 }
@@ -717,8 +733,8 @@ int run_relin(const hentt_tables *t, const uint64_t *c, const uint64_t *ksk, uin
   Storage *s = t->s;
   const uint32_t ln = s->log_n, L1 = t->limbs, l = L1 - 1;
   const uint64_t N = 1ull << ln, P = (uint64_t)l * N;
-  const uint64_t *mu = nullptr;
-  int rc = ks_mu(s, &mu);
+  const KsLimb *kc = nullptr;
+  int rc = ks_consts(s, L1, &kc);
   if (rc) return rc;
   const bool two_pass = ln > 12;  // KsPlan<>::WHOLE
   const size_t d_bytes = (size_t)batch * P * 8, acc_bytes = (size_t)batch * 2 * L1 * N * 8;
@@ -737,19 +753,15 @@ int run_relin(const hentt_tables *t, const uint64_t *c, const uint64_t *ksk, uin
     a.ksk = ksk;
     a.e = two_pass ? e : nullptr;
     a.acc = acc;
-    a.mu = mu;
+    a.c = c;
+    a.kc = kc;
     a.batch = batch;
     a.l = l;
     k_ks_table[ln - HENTT_LOG_N_MIN](a, s, st);
     he = hipGetLastError();
-    // divide by P with rounding, over q_0 .. q_{l-1}: [batch][2][l+1] -> [batch][2][l]
+    // divide by P with rounding, over q_0 .. q_{l-1}: [batch][2][l+1] -> [batch][2][l];
+    // the accumulators already hold P c_s, so this yields (c0, c1) + round(P^-1 c2 evk)
     if (he == hipSuccess) rc = run_rescale(t, acc, out, batch * 2, true, st);
-    if (he == hipSuccess && !rc) {
-      const uint32_t tiles = (uint32_t)((N + 2047) / 2048);
-      LaunchTimer lt_("k_ks_add", (int)ln, st);
-      hipLaunchKernelGGL(k_ks_add, dim3(batch * 2 * l * tiles), dim3(256), 0, st, c, out, s->d_lc, l, ln, tiles);
-      he = hipGetLastError();
-    }
   }
   pool_put(buf);
   if (rc) return rc;

@@ -7,18 +7,32 @@
 // with the key-switching key are accumulated in registers over the digits
 // (fused into the transform's last stage):
 //   acc_s[t] = sum_j NTT_t(d_j mod q_t) . ksk[j][s][t]   (s = 0, 1).
-// The division by P with rounding is the rescale of rescale_kernels.hpp.
+// The products are Montgomery products (R = 2^64) on the lazy transform
+// outputs, summed lazily below 2 q_t; one Shoup product by R mod q_t per
+// output word removes the common factor R^-1 before the store.  The same
+// epilogue adds P c_s (s = 0, 1) for t < l: round((x + P c_s) / P) =
+// c_s + round(x / P) exactly (x and x + P c_s agree mod P), so the rescale
+// of rescale_kernels.hpp that divides by P with rounding also completes
+// c' = (c0, c1) + round(P^-1 c2 evk).
 #pragma once
 #include "ntt_kernels.hpp"
 
 namespace hentt {
+
+struct KsLimb {     // per target prime q_t of one level
+  uint64_t mu;      // floor(2^64 / q_t)
+  uint64_t qinv;    // -q_t^-1 mod 2^64
+  uint64_t r, rs;   // 2^64 mod q_t and its Shoup quotient
+  uint64_t pm, pms; // P mod q_t and its Shoup quotient (t < l)
+};
 
 struct KsArgs {
   const uint64_t *d;    // [batch][l][N] digits, coefficient domain, canonical mod q_j
   const uint64_t *ksk;  // [l][2][l + 1][N] NTT domain
   uint64_t *e;          // [batch][l][l + 1][N] column-pass scratch (two-pass sizes)
   uint64_t *acc;        // [batch][2][l + 1][N]
-  const uint64_t *mu;   // [l + 1]: floor(2^64 / q_t)
+  const uint64_t *c;    // [batch][3][l][N] NTT domain: (c0, c1) enter as P c_s
+  const KsLimb *kc;     // [l + 1]
   uint32_t batch, l;
 };
 
@@ -27,21 +41,49 @@ struct KsArgs {
 // lazy input of the forward transform.
 __device__ __forceinline__ uint64_t ks_lift(uint64_t x, uint64_t mu, uint64_t q) { return x - mulhi64(x, mu) * q; }
 
-// acc0 += v . key0, acc1 += v . key1 (mod q, one reduction each) for the
-// words of v held in the (0, E) map of a 2^B block; key0 at k, key1 one
-// prime-row further (`row` blocks of 2^B words).  The two products run one
-// after the other (scheduling barrier) so that only one key array is live.
+// acc0 += v . key0 R^-1, acc1 += v . key1 R^-1 (mod q, accumulators kept
+// in [0, 2q)) for the words of v (lazy forward outputs below 8q, so that
+// v . key < 8 q^2 < q R) held in the (0, E) map of a 2^B block; key0 at k,
+// key1 one prime-row further (`row` blocks of 2^B words).  The two products
+// run one after the other (scheduling barrier) so that only one key array is
+// live.
 template <int B, int E>
 __device__ __forceinline__ void ks_mac(const uint64_t (&v)[1 << E], const uint64_t *k, uint32_t row, uint32_t lp,
-                                       uint64_t (&acc0)[1 << E], uint64_t (&acc1)[1 << E], const LimbConst &c) {
+                                       uint64_t (&acc0)[1 << E], uint64_t (&acc1)[1 << E], const ModQ &m,
+                                       uint64_t qinv) {
   uint64_t kv[1 << E];
   load_global<B, E, 0, E>(kv, k, lp);
 #pragma unroll
-  for (int s = 0; s < (1 << E); ++s) acc0[s] = mac1mod(v[s], kv[s], acc0[s], c.m.q, c.mu, c.k);
+  for (int s = 0; s < (1 << E); ++s) acc0[s] = csubn(acc0[s] + mont_mul(v[s], kv[s], m.q, qinv), m.nq2);
   __builtin_amdgcn_sched_barrier(0);
   load_global<B, E, 0, E>(kv, k + ((uint64_t)row << B), lp);
 #pragma unroll
-  for (int s = 0; s < (1 << E); ++s) acc1[s] = mac1mod(v[s], kv[s], acc1[s], c.m.q, c.mu, c.k);
+  for (int s = 0; s < (1 << E); ++s) acc1[s] = csubn(acc1[s] + mont_mul(v[s], kv[s], m.q, qinv), m.nq2);
+}
+
+// Accumulators (sums of Montgomery products, [0, 2q)) to canonical values:
+// times R mod q by a Shoup product, plus P c_s when cs (c_s's words of the
+// block, in the (0, E) map) is given; each Shoup product lies in [0, 4q).
+template <int B, int E>
+__device__ __forceinline__ void ks_finish(uint64_t (&acc)[1 << E], const KsLimb &kc, const ModQ &m,
+                                          const uint64_t *cs, uint32_t lp) {
+  if (cs) {
+    uint64_t cv[1 << E];
+    load_global<B, E, 0, E>(cv, cs, lp);
+#pragma unroll
+    for (int s = 0; s < (1 << E); ++s)
+      acc[s] = reduce_8q(shoup(kc.r, kc.rs, acc[s], m.nq) + shoup(kc.pm, kc.pms, cv[s], m.nq), m);
+  } else {
+#pragma unroll
+    for (int s = 0; s < (1 << E); ++s) acc[s] = reduce_4q(shoup(kc.r, kc.rs, acc[s], m.nq), m);
+  }
+}
+
+// c_s's words (s = 0, 1) at block offset `off` of target prime t for batch
+// entry b, or null for the special prime (t = l).
+__device__ __forceinline__ const uint64_t *ks_cs(const KsArgs &a, uint32_t b, uint32_t s, uint32_t t, int logn,
+                                                 uint32_t off) {
+  return t < a.l ? a.c + ((((uint64_t)b * 3 + s) * a.l + t) << logn) + off : nullptr;
 }
 
 // Whole transforms (N <= 2^12, 256 lanes): one workgroup per (batch entry,
@@ -53,7 +95,7 @@ __global__ __launch_bounds__(1 << (LOGN - E)) void k_ks_whole(KsArgs a, const Tw
   const uint32_t L1 = a.l + 1;
   const uint32_t t = blockIdx.x / a.batch, b = blockIdx.x % a.batch;
   const LimbConst c = lc[t];
-  const uint64_t mu = a.mu[t];
+  const KsLimb kc = a.kc[t];
   const Tw *tt = tw + (size_t)t * 2 * (1u << LOGN);
   const uint32_t tid = threadIdx.x;
   using F = FwdFirst<LOGN, E>;
@@ -68,14 +110,16 @@ __global__ __launch_bounds__(1 << (LOGN - E)) void k_ks_whole(KsArgs a, const Tw
     load_global<LOGN, E, F::LO, F::R>(v, a.d + (((uint64_t)b * a.l + j) << LOGN),
                                        RoundMap<LOGN, E, F::LO, F::R>::lane_part(tid));
 #pragma unroll
-    for (int s = 0; s < (1 << E); ++s) v[s] = ks_lift(v[s], mu, c.m.q);
+    for (int s = 0; s < (1 << E); ++s) v[s] = ks_lift(v[s], kc.mu, c.m.q);
     // an opaque copy of the table pointer per digit: the twiddles (the same
     // for every digit) are re-read from cache instead of held in VGPRs
     fwd_block_rounds<LOGN, E, F::LO, F::R>(v, LOGN, lds, tid, 0, opaque(tt), c.m);
-    reduce_fwd<E>(v, c.m);
-    ks_mac<LOGN, E>(v, a.ksk + (((uint64_t)j * 2 * L1 + t) << LOGN), L1, M0::lane_part(tid), acc0, acc1, c);
+    ks_mac<LOGN, E>(v, a.ksk + (((uint64_t)j * 2 * L1 + t) << LOGN), L1, M0::lane_part(tid), acc0, acc1, c.m,
+                    kc.qinv);
   }
+  ks_finish<LOGN, E>(acc0, kc, c.m, ks_cs(a, b, 0, t, LOGN, 0), M0::lane_part(tid));
   store_global<LOGN, E, 0, E>(acc0, a.acc + (((uint64_t)b * 2 * L1 + t) << LOGN), M0::lane_part(tid));
+  ks_finish<LOGN, E>(acc1, kc, c.m, ks_cs(a, b, 1, t, LOGN, 0), M0::lane_part(tid));
   store_global<LOGN, E, 0, E>(acc1, a.acc + (((uint64_t)(b * 2 + 1) * L1 + t) << LOGN), M0::lane_part(tid));
 }
 
@@ -92,7 +136,7 @@ __global__ __launch_bounds__(256) void k_ks_cols(KsArgs a, const Tw *__restrict_
   r /= L1;
   const uint32_t j = r % a.l, b = r / a.l;
   const ModQ m = lc[t].m;
-  const uint64_t mu = a.mu[t];
+  const uint64_t mu = a.kc[t].mu;
   uint64_t v[1 << EC];
   load_global<LOGN, EC, LO, EC, true>(v, a.d + (((uint64_t)b * a.l + j) << LOGN), col);
 #pragma unroll
@@ -113,6 +157,7 @@ __global__ __launch_bounds__(1 << (B - E)) void k_ks_blocks(KsArgs a, const Tw *
   const uint32_t r = blockIdx.x / tiles;
   const uint32_t t = r / a.batch, b = r % a.batch;
   const LimbConst c = lc[t];
+  const KsLimb kc = a.kc[t];
   const Tw *tt = tw + (size_t)t * 2 * (1u << LOGN);
   const uint32_t tid = threadIdx.x;
   using F = FwdFirst<B, E>;
@@ -127,36 +172,14 @@ __global__ __launch_bounds__(1 << (B - E)) void k_ks_blocks(KsArgs a, const Tw *
     load_global<B, E, F::LO, F::R>(v, a.e + ((((uint64_t)b * a.l + j) * L1 + t) << LOGN) + blockStart,
                                    RoundMap<B, E, F::LO, F::R>::lane_part(tid));
     fwd_block_rounds<B, E, F::LO, F::R>(v, LOGN, lds, tid, blockStart, opaque(tt), c.m);
-    reduce_fwd<E>(v, c.m);
     ks_mac<B, E>(v, a.ksk + (((uint64_t)j * 2 * L1 + t) << LOGN) + blockStart, L1 << (LOGN - B),
-                 M0::lane_part(tid), acc0, acc1, c);
+                 M0::lane_part(tid), acc0, acc1, c.m, kc.qinv);
   }
+  ks_finish<B, E>(acc0, kc, c.m, ks_cs(a, b, 0, t, LOGN, blockStart), M0::lane_part(tid));
   store_global<B, E, 0, E>(acc0, a.acc + (((uint64_t)b * 2 * L1 + t) << LOGN) + blockStart, M0::lane_part(tid));
+  ks_finish<B, E>(acc1, kc, c.m, ks_cs(a, b, 1, t, LOGN, blockStart), M0::lane_part(tid));
   store_global<B, E, 0, E>(acc1, a.acc + (((uint64_t)(b * 2 + 1) * L1 + t) << LOGN) + blockStart,
                            M0::lane_part(tid));
-}
-
-// out[b][s] += c[b][s] (s = 0, 1) modulo q_i: the key-switched terms added to
-// (c0, c1); c is [batch][3][l][N], out [batch][2][l][N].  One workgroup per
-// (batch entry, component, limb, tile of 2048 words): the limb is uniform.
-__global__ __launch_bounds__(256) void k_ks_add(const uint64_t *__restrict__ c, uint64_t *__restrict__ out,
-                                                const LimbConst *__restrict__ lc, uint32_t l, uint32_t log_n,
-                                                uint32_t tiles) {
-  const uint32_t tile = blockIdx.x % tiles, r = blockIdx.x / tiles;
-  const uint32_t limb = r % l, bs = r / l;  // bs = 2 b + s
-  const uint64_t q = lc[limb].m.q;
-  const uint64_t P = (uint64_t)l << log_n;
-  const uint64_t *src = c + (uint64_t)(bs / 2) * 3 * P + (uint64_t)(bs % 2) * P + ((uint64_t)limb << log_n);
-  uint64_t *dst = out + (uint64_t)bs * P + ((uint64_t)limb << log_n);
-  const uint32_t n = 1u << log_n;
-#pragma unroll
-  for (int s = 0; s < 8; ++s) {
-    const uint32_t k = tile * 2048u + threadIdx.x + 256u * s;
-    if (k < n) {
-      const uint64_t v = dst[k] + src[k];
-      dst[k] = v >= q ? v - q : v;
-    }
-  }
 }
 
 }  // namespace hentt
