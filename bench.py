@@ -249,7 +249,7 @@ VALU_BFLY = 21     # Harvey/Shoup butterfly: 9 32-bit multiplies + 12 adds, comp
 VALU_PROD = 19     # Montgomery product a b R^-1 mod q: 128-bit product, low product by -q^-1, high product by q
 VALU_TENSOR = 68   # c0d0, c1d1 (2 x 19) + c0d1 + c1d0 with one Montgomery reduction (30)
 VALU_RS_EPI = 17   # rescale epilogue: Shoup product by qL^-1 (9 + adds) and a reduction from [0, 4q)
-VALU_MAC = 121     # one matMul product term: the tensor's three outputs accumulated with mad_mod
+VALU_MAC = 83      # one matMul product term: the tensor's Montgomery products (68) and three lazy additions (5 each)
 
 
 def kernel_work(name, info):

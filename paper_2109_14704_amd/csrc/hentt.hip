@@ -114,7 +114,7 @@ struct Storage {
   Tw *d_tw = nullptr;          // [limbs][2][N]
   LimbConst *d_lc = nullptr;   // [limbs]
   LimbConst *d_lcm = nullptr;  // [limbs] the same with N^-1 R mod q for N^-1 (after Montgomery products)
-  uint64_t *d_qinv = nullptr;  // [limbs] -q^-1 mod 2^64
+  MontLimb *d_mont = nullptr;  // [limbs] Montgomery constants
   std::vector<uint64_t> moduli;
   int device = 0;
   std::mutex rs_mu;            // rescale constants per level (limb count), made on first use
@@ -130,7 +130,7 @@ void release(Storage *s) {
     if (s->d_tw) (void)hipFree(s->d_tw);
     if (s->d_lc) (void)hipFree(s->d_lc);
     if (s->d_lcm) (void)hipFree(s->d_lcm);
-    if (s->d_qinv) (void)hipFree(s->d_qinv);
+    if (s->d_mont) (void)hipFree(s->d_mont);
     for (auto &kv : s->rs) (void)hipFree(kv.second);
     for (auto &kv : s->ks) (void)hipFree(kv.second);
     (void)hipSetDevice(cur);
@@ -329,7 +329,7 @@ void launch_prod(const hentt_tables *t, const ProdArgs &pa, uint32_t batch, bool
   // outputs going back to the coefficient domain take Montgomery products,
   // whose R^-1 the inverse transform's folded N^-1 R scaling cancels
   const LimbConst *lc = out_coeff ? t->s->d_lcm : t->s->d_lc;
-  const uint64_t *qinv = t->s->d_qinv;
+  const MontLimb *mont = t->s->d_mont;
   const uint32_t L = t->limbs;
   const uint32_t units = batch * L;
   constexpr int NIN = ProdShape<MODE>::NIN, NOUT = ProdShape<MODE>::NOUT;
@@ -342,9 +342,9 @@ void launch_prod(const hentt_tables *t, const ProdArgs &pa, uint32_t batch, bool
   constexpr int PE = ProdE<MODE>::E;
   if constexpr (P::PROD_WHOLE) {
     const dim3 g(units), blk(1 << (LOGN - PE));
-    if (in_coeff && out_coeff) { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, LOGN, PE, MODE, true, true>), g, blk, prod_lds_pad(), st, pa, tw, lc, qinv, batch, L); }
-    else if (in_coeff) { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, LOGN, PE, MODE, true, false>), g, blk, prod_lds_pad(), st, pa, tw, lc, qinv, batch, L); }
-    else { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, LOGN, PE, MODE, false, true>), g, blk, prod_lds_pad(), st, pa, tw, lc, qinv, batch, L); }
+    if (in_coeff && out_coeff) { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, LOGN, PE, MODE, true, true>), g, blk, prod_lds_pad(), st, pa, tw, lc, mont, batch, L); }
+    else if (in_coeff) { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, LOGN, PE, MODE, true, false>), g, blk, prod_lds_pad(), st, pa, tw, lc, mont, batch, L); }
+    else { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, LOGN, PE, MODE, false, true>), g, blk, prod_lds_pad(), st, pa, tw, lc, mont, batch, L); }
   } else {
     constexpr int EC = P::PEC, B = LOGN - P::PEC;
     const uint64_t NL = (uint64_t)L << LOGN;
@@ -364,9 +364,9 @@ void launch_prod(const hentt_tables *t, const ProdArgs &pa, uint32_t batch, bool
                          ca, tw, lc, batch, L); }
     }
     const dim3 g(units << (LOGN - B)), blk(1 << (B - PE));
-    if (in_coeff && out_coeff) { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, B, PE, MODE, true, true>), g, blk, prod_lds_pad(), st, pb, tw, lc, qinv, batch, L); }
-    else if (in_coeff) { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, B, PE, MODE, true, false>), g, blk, prod_lds_pad(), st, pb, tw, lc, qinv, batch, L); }
-    else { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, B, PE, MODE, false, true>), g, blk, prod_lds_pad(), st, pb, tw, lc, qinv, batch, L); }
+    if (in_coeff && out_coeff) { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, B, PE, MODE, true, true>), g, blk, prod_lds_pad(), st, pb, tw, lc, mont, batch, L); }
+    else if (in_coeff) { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, B, PE, MODE, true, false>), g, blk, prod_lds_pad(), st, pb, tw, lc, mont, batch, L); }
+    else { LaunchTimer lt_(MODE == PROD_MUL ? "k_prod_mul" : "k_prod_tensor", LOGN, st); hipLaunchKernelGGL((k_prod<LOGN, B, PE, MODE, false, true>), g, blk, prod_lds_pad(), st, pb, tw, lc, mont, batch, L); }
     if (out_coeff) {
       ColArgs ca{};
       for (int o = 0; o < NOUT; ++o) ca.src[o] = ca.dst[o] = pa.out[o];
@@ -647,7 +647,7 @@ int run_rescale(const hentt_tables *t, const uint64_t *c, uint64_t *out, uint32_
     last.d_tw = s->d_tw + (size_t)L * 2 * N;
     last.d_lc = s->d_lc + L;
     last.d_lcm = s->d_lcm + L;
-    last.d_qinv = s->d_qinv + L;
+    last.d_mont = s->d_mont + L;
     last.device = s->device;
     const hentt_tables lv{&last, 1};
     rc = run_transform(&lv, (uint64_t *)tl, batch, st, true);
@@ -864,7 +864,7 @@ int hentt_tables_create(uint32_t log_n, uint32_t limbs, const uint64_t *moduli_h
   const uint32_t N = 1u << log_n;
   std::vector<Tw> tw((size_t)limbs * 2 * N);
   std::vector<LimbConst> lc(limbs), lcm(limbs);
-  std::vector<uint64_t> qinv(limbs);
+  std::vector<MontLimb> mont(limbs);
   std::vector<uint64_t> pw(N), ipw(N);
   for (uint32_t l = 0; l < limbs; ++l) {
     const uint64_t q = moduli_host[l];
@@ -898,8 +898,8 @@ int hentt_tables_create(uint32_t log_n, uint32_t limbs, const uint64_t *moduli_h
     c.mu = (uint64_t)(((u128)1 << (2 * c.k)) / q);
     uint64_t qi = q;  // q^-1 mod 2^64 by Newton's iteration (3 -> 96 bits)
     for (int i = 0; i < 5; ++i) qi *= 2 - q * qi;
-    qinv[l] = 0 - qi;
     const uint64_t r = (uint64_t)(((u128)1 << 64) % q);
+    mont[l] = MontLimb{0 - qi, r, shoup_quot(r, q), 0};
     LimbConst &cm = lcm[l];
     cm = c;
     cm.ninv = h_mul(c.ninv, r, q);
@@ -918,13 +918,13 @@ int hentt_tables_create(uint32_t log_n, uint32_t limbs, const uint64_t *moduli_h
   if (e == hipSuccess) e = hipMalloc(&s->d_lc, lc.size() * sizeof(LimbConst));
   if (e == hipSuccess) e = hipMemcpyAsync(s->d_tw, tw.data(), tw.size() * sizeof(Tw), hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipMalloc(&s->d_lcm, lcm.size() * sizeof(LimbConst));
-  if (e == hipSuccess) e = hipMalloc(&s->d_qinv, qinv.size() * sizeof(uint64_t));
+  if (e == hipSuccess) e = hipMalloc(&s->d_mont, mont.size() * sizeof(MontLimb));
   if (e == hipSuccess)
     e = hipMemcpyAsync(s->d_lc, lc.data(), lc.size() * sizeof(LimbConst), hipMemcpyHostToDevice, st);
   if (e == hipSuccess)
     e = hipMemcpyAsync(s->d_lcm, lcm.data(), lcm.size() * sizeof(LimbConst), hipMemcpyHostToDevice, st);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(s->d_qinv, qinv.data(), qinv.size() * sizeof(uint64_t), hipMemcpyHostToDevice, st);
+    e = hipMemcpyAsync(s->d_mont, mont.data(), mont.size() * sizeof(MontLimb), hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) {
     release(s);
@@ -1009,8 +1009,11 @@ int hentt_ct_matmul(const hentt_tables *t, const uint64_t *A, const uint64_t *B,
   if (grid > 0x7fffffffu) return HENTT_EINVAL;
   hipStream_t st = (hipStream_t)stream;
   LaunchTimer lt_("k_ct_matmul", (int)t->s->log_n, st);
-  hipLaunchKernelGGL(k_ct_matmul, dim3((uint32_t)grid), dim3(256), 0, st, A, B, C, t->s->d_lc, m, n, k, t->limbs,
-                     t->s->log_n, tiles);
+  const bool full = N >= 2048, mont = k >= 3;  // Montgomery accumulation pays from k = 3 on
+  auto kern = full ? (mont ? k_ct_matmul<true, true> : k_ct_matmul<true, false>)
+                   : (mont ? k_ct_matmul<false, true> : k_ct_matmul<false, false>);
+  hipLaunchKernelGGL(kern, dim3((uint32_t)grid), dim3(256), 0, st, A, B, C, t->s->d_lc, t->s->d_mont, m, n, k,
+                     t->limbs, t->s->log_n, tiles);
   HIPCHK(hipGetLastError());
   return HENTT_OK;
 }

@@ -31,6 +31,13 @@ struct LimbConst {
 
 static_assert(sizeof(LimbConst) == 96, "limb records are 12 words (documented in the C ABI)");
 
+// Montgomery constants of a limb (R = 2^64).
+struct MontLimb {
+  uint64_t qinv;   // -q^-1 mod 2^64
+  uint64_t r, rs;  // R mod q and its Shoup quotient
+  uint64_t pad;
+};
+
 struct alignas(16) Tw { uint64_t w, ws; };
 
 // LDS padding: one spare element after every 16, so that the lane-strided
@@ -519,13 +526,12 @@ template <int MODE, int E> __device__ __forceinline__ void reduce_for_mont(uint6
 // with B < LOGN the forward column pass runs before it and the inverse
 // column pass after it.  With DO_INV the products are Montgomery products
 // and lc must hold the folded constants (N^-1 R in place of N^-1), also for
-// the inverse column pass that completes the transform; qinv[limb] is
-// -q^-1 mod 2^64.  Without DO_INV the products are exact (Barrett) and lc
-// the plain constants.
+// the inverse column pass that completes the transform.  Without DO_INV the
+// products are exact (Barrett) and lc the plain constants.
 template <int LOGN, int B, int E, int MODE, bool DO_FWD, bool DO_INV>
 __global__ __launch_bounds__(1 << (B - E)) void k_prod(ProdArgs a, const Tw *__restrict__ tw,
                                                         const LimbConst *__restrict__ lc,
-                                                        const uint64_t *__restrict__ qinv, uint32_t batch,
+                                                        const MontLimb *__restrict__ mont, uint32_t batch,
                                                         uint32_t limbs) {
   constexpr int NIN = ProdShape<MODE>::NIN, NOUT = ProdShape<MODE>::NOUT;
   __shared__ uint64_t lds[(DO_FWD || DO_INV) ? LdsSize<B>::value : 2];
@@ -574,7 +580,7 @@ __global__ __launch_bounds__(1 << (B - E)) void k_prod(ProdArgs a, const Tw *__r
     });
   }
   uint64_t Y[NOUT][1 << E];
-  if constexpr (DO_INV) products_mont<MODE, E>(X, Y, c.m.q, qinv[limb]);
+  if constexpr (DO_INV) products_mont<MODE, E>(X, Y, c.m.q, mont[limb].qinv);
   else products<MODE, E>(X, Y, c);
 #pragma unroll 1
   for (int o = 0; o < NOUT; ++o) {
@@ -599,14 +605,83 @@ __global__ __launch_bounds__(1 << (B - E)) void k_prod(ProdArgs a, const Tw *__r
 
 // Encrypted element-wise polynomial matrix product (section IV-E), NTT
 // domain: C (m x n) += A (m x k) * B (k x n) with ciphertext elements, every
-// element product the Mul tensor accumulated with one reduction per
-// multiply-add.  One workgroup per (limb, i, j, tile of 2048 coefficients),
-// j and the tile fastest so that consecutive workgroups share A's tiles in
-// L2; 8 coefficients per lane, the three accumulators in registers over k.
+// element product the Mul tensor with one reduction per output (the middle
+// term's two products summed first, mad_mod).  For k >= 3 the reductions are
+// Montgomery's (R = 2^64): the accumulators start from C R^-1 (a Montgomery
+// reduction of C itself, taken in the first step after the loads of A and B
+// are issued, so that all three overlap), take the products' sums lazily
+// below 2q over k, and one Shoup product by R mod q per word removes the
+// common R^-1.  That conversion costs about as much as two and a half
+// multiply-adds save, so smaller k accumulate with Barrett (mac1mod,
+// mac2mod) directly on C (the host picks the instance; FULL when N >= 2048).
+// One workgroup per (limb, i, j, tile of 2048 coefficients), j and
+// the tile fastest so that consecutive workgroups share A's tiles in L2; 8
+// coefficients per lane, the three accumulators in registers over k.
+// One tile of k_ct_matmul.  FULL: every word of the tile lies below N (all
+// tiles when N >= 2048), so the loads carry no per-word guard and are issued
+// together; otherwise words at or beyond N are skipped.  MONT: Montgomery
+// accumulation, else Barrett.
+template <bool FULL, bool MONT>
+__device__ __forceinline__ void ct_matmul_tile(const uint64_t *A, const uint64_t *B, uint64_t *c,
+                                               const LimbConst &lc, const MontLimb &mc, uint64_t P, uint64_t off,
+                                               uint32_t ia, uint32_t jb, uint32_t n, uint32_t k, uint32_t valid) {
+  const ModQ &mq = lc.m;
+  const uint64_t q = mq.q, qinv = mc.qinv;
+  uint64_t c0[8], c1[8], c2[8];
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const uint32_t e = threadIdx.x + 256u * s;
+    const bool in = FULL || e < valid;
+    c0[s] = in ? c[e] : 0;
+    c1[s] = in ? c[P + e] : 0;
+    c2[s] = in ? c[2 * P + e] : 0;
+  }
+  for (uint32_t l = 0; l < k; ++l) {
+    const uint64_t *a = A + ((uint64_t)ia * k + l) * 2 * P + off;
+    const uint64_t *b = B + ((uint64_t)l * n + jb) * 2 * P + off;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const uint32_t e = threadIdx.x + 256u * s;
+      if (FULL || e < valid) {
+        const uint64_t a0 = a[e], a1 = a[P + e], b0 = b[e], b1 = b[P + e];
+        if constexpr (MONT) {
+          if (l == 0) {
+            c0[s] = redc(0, c0[s], q, qinv);
+            c1[s] = redc(0, c1[s], q, qinv);
+            c2[s] = redc(0, c2[s], q, qinv);
+          }
+          c0[s] = csubn(c0[s] + mont_mul(a0, b0, q, qinv), mq.nq2);
+          c1[s] = csubn(c1[s] + mont_mad(a0, b1, a1, b0, q, qinv), mq.nq2);
+          c2[s] = csubn(c2[s] + mont_mul(a1, b1, q, qinv), mq.nq2);
+        } else {
+          c0[s] = mac1mod(a0, b0, c0[s], q, lc.mu, lc.k);
+          c1[s] = mac2mod(a0, b1, a1, b0, c1[s], q, lc.mu, lc.k);
+          c2[s] = mac1mod(a1, b1, c2[s], q, lc.mu, lc.k);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    const uint32_t e = threadIdx.x + 256u * s;
+    if (FULL || e < valid) {
+      if constexpr (MONT) {
+        c0[s] = reduce_4q(shoup(mc.r, mc.rs, c0[s], mq.nq), mq);
+        c1[s] = reduce_4q(shoup(mc.r, mc.rs, c1[s], mq.nq), mq);
+        c2[s] = reduce_4q(shoup(mc.r, mc.rs, c2[s], mq.nq), mq);
+      }
+      c[e] = c0[s];
+      c[P + e] = c1[s];
+      c[2 * P + e] = c2[s];
+    }
+  }
+}
+
+template <bool FULL, bool MONT>
 __global__ __launch_bounds__(256) void k_ct_matmul(const uint64_t *__restrict__ A, const uint64_t *__restrict__ B,
                                                    uint64_t *__restrict__ C, const LimbConst *__restrict__ lc,
-                                                   uint32_t m, uint32_t n, uint32_t k, uint32_t limbs,
-                                                   uint32_t log_n, uint32_t tiles) {
+                                                   const MontLimb *__restrict__ mont, uint32_t m, uint32_t n,
+                                                   uint32_t k, uint32_t limbs, uint32_t log_n, uint32_t tiles) {
   uint32_t r = blockIdx.x;
   const uint32_t tile = r % tiles;
   r /= tiles;
@@ -614,43 +689,11 @@ __global__ __launch_bounds__(256) void k_ct_matmul(const uint64_t *__restrict__ 
   r /= n;
   const uint32_t i = r % m, limb = r / m;
   const LimbConst cst = lc[limb];
-  const uint64_t q = cst.m.q, mu = cst.mu;
-  const uint32_t kb = cst.k, N = 1u << log_n;
+  const MontLimb mc = mont[limb];
   const uint64_t P = (uint64_t)limbs << log_n;
   const uint64_t off = ((uint64_t)limb << log_n) + tile * 2048u;
   uint64_t *c = C + ((uint64_t)i * n + j) * 3 * P + off;
-  uint64_t c0[8], c1[8], c2[8];
-#pragma unroll
-  for (int s = 0; s < 8; ++s) {
-    const uint32_t e = threadIdx.x + 256u * s;
-    const bool in = tile * 2048u + e < N;
-    c0[s] = in ? c[e] : 0;
-    c1[s] = in ? c[P + e] : 0;
-    c2[s] = in ? c[2 * P + e] : 0;
-  }
-  for (uint32_t l = 0; l < k; ++l) {
-    const uint64_t *a = A + ((uint64_t)i * k + l) * 2 * P + off;
-    const uint64_t *b = B + ((uint64_t)l * n + j) * 2 * P + off;
-#pragma unroll
-    for (int s = 0; s < 8; ++s) {
-      const uint32_t e = threadIdx.x + 256u * s;
-      if (tile * 2048u + e < N) {
-        const uint64_t a0 = a[e], a1 = a[P + e], b0 = b[e], b1 = b[P + e];
-        c0[s] = mac1mod(a0, b0, c0[s], q, mu, kb);
-        c1[s] = mac2mod(a0, b1, a1, b0, c1[s], q, mu, kb);
-        c2[s] = mac1mod(a1, b1, c2[s], q, mu, kb);
-      }
-    }
-  }
-#pragma unroll
-  for (int s = 0; s < 8; ++s) {
-    const uint32_t e = threadIdx.x + 256u * s;
-    if (tile * 2048u + e < N) {
-      c[e] = c0[s];
-      c[P + e] = c1[s];
-      c[2 * P + e] = c2[s];
-    }
-  }
+  ct_matmul_tile<FULL, MONT>(A, B, c, cst, mc, P, off, i, j, n, k, FULL ? 2048u : (1u << log_n));
 }
 
 // Element-wise products of NTT-domain inputs (no transform): tiles of 2048

@@ -181,7 +181,7 @@ def test_rescale_level_views_and_errors(gpu):
     assert rc != 0                                           # only both-or-neither NTT flags
 
 
-@pytest.mark.parametrize("m,n,k,log_n", [(2, 3, 2, 13), (5, 4, 1, 12), (10, 9, 8, 6), (3, 2, 3, 13)])
+@pytest.mark.parametrize("m,n,k,log_n", [(2, 3, 2, 13), (5, 4, 1, 12), (10, 9, 8, 6), (3, 2, 3, 13), (4, 3, 2, 8)])
 def test_ct_matmul(gpu, m, n, k, log_n):
     """Encrypted element-wise polynomial matrix product, element by element."""
     import paper_2109_14704_amd as H
