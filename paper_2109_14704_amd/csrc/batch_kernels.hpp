@@ -40,7 +40,7 @@ __device__ __forceinline__ void batch_fwd_block(uint64_t *p, uint32_t blockStart
   load_global<BATCH_B, BATCH_E, F::LO, F::R>(v, p, RoundMap<BATCH_B, BATCH_E, F::LO, F::R>::lane_part(tid));
   fwd_block_rounds<BATCH_B, BATCH_E, F::LO, F::R>(v, logn, lds, tid, blockStart, t, m);
   reduce_fwd<BATCH_E>(v, m);
-  store_global<BATCH_B, BATCH_E, 0, BATCH_E>(v, p, RoundMap<BATCH_B, BATCH_E, 0, BATCH_E>::lane_part(tid));
+  store_global_m0<BATCH_B, BATCH_E>(v, p, lds, tid);
 }
 
 // Inverse block pass (stages 0 .. 11); canonical when it is the whole transform.
@@ -48,7 +48,7 @@ __device__ __forceinline__ void batch_inv_block(uint64_t *p, uint32_t blockStart
                                                 const LimbConst &c, uint64_t *lds, uint32_t tid) {
   using L = InvLast<BATCH_B, BATCH_E>;
   uint64_t v[1 << BATCH_E];
-  load_global<BATCH_B, BATCH_E, 0, BATCH_E>(v, p, RoundMap<BATCH_B, BATCH_E, 0, BATCH_E>::lane_part(tid));
+  load_global_m0<BATCH_B, BATCH_E>(v, p, lds, tid);
   inv_block_rounds<BATCH_B, BATCH_E, 0, BATCH_E>(v, logn, lds, tid, blockStart, it, c);
   if (logn == BATCH_B) reduce_inv<BATCH_E>(v, c.m);
   store_global<BATCH_B, BATCH_E, L::LO, L::R>(v, p, RoundMap<BATCH_B, BATCH_E, L::LO, L::R>::lane_part(tid));

@@ -118,9 +118,9 @@ __global__ __launch_bounds__(1 << (LOGN - E)) void k_ks_whole(KsArgs a, const Tw
                     kc.qinv);
   }
   ks_finish<LOGN, E>(acc0, kc, c.m, ks_cs(a, b, 0, t, LOGN, 0), M0::lane_part(tid));
-  store_global<LOGN, E, 0, E>(acc0, a.acc + (((uint64_t)b * 2 * L1 + t) << LOGN), M0::lane_part(tid));
+  store_global_m0<LOGN, E>(acc0, a.acc + (((uint64_t)b * 2 * L1 + t) << LOGN), lds, tid);
   ks_finish<LOGN, E>(acc1, kc, c.m, ks_cs(a, b, 1, t, LOGN, 0), M0::lane_part(tid));
-  store_global<LOGN, E, 0, E>(acc1, a.acc + (((uint64_t)(b * 2 + 1) * L1 + t) << LOGN), M0::lane_part(tid));
+  store_global_m0<LOGN, E>(acc1, a.acc + (((uint64_t)(b * 2 + 1) * L1 + t) << LOGN), lds, tid);
 }
 
 // Two-pass sizes, pass 1: column pass of digit j modulo q_t into e.
@@ -176,10 +176,9 @@ __global__ __launch_bounds__(1 << (B - E)) void k_ks_blocks(KsArgs a, const Tw *
                  M0::lane_part(tid), acc0, acc1, c.m, kc.qinv);
   }
   ks_finish<B, E>(acc0, kc, c.m, ks_cs(a, b, 0, t, LOGN, blockStart), M0::lane_part(tid));
-  store_global<B, E, 0, E>(acc0, a.acc + (((uint64_t)b * 2 * L1 + t) << LOGN) + blockStart, M0::lane_part(tid));
+  store_global_m0<B, E>(acc0, a.acc + (((uint64_t)b * 2 * L1 + t) << LOGN) + blockStart, lds, tid);
   ks_finish<B, E>(acc1, kc, c.m, ks_cs(a, b, 1, t, LOGN, blockStart), M0::lane_part(tid));
-  store_global<B, E, 0, E>(acc1, a.acc + (((uint64_t)(b * 2 + 1) * L1 + t) << LOGN) + blockStart,
-                           M0::lane_part(tid));
+  store_global_m0<B, E>(acc1, a.acc + (((uint64_t)(b * 2 + 1) * L1 + t) << LOGN) + blockStart, lds, tid);
 }
 
 }  // namespace hentt

@@ -197,6 +197,48 @@ __device__ __forceinline__ void store_lds(const uint64_t (&x)[1 << E], uint64_t*
   for (int s = 0; s < (1 << E); ++s) lds[lds_pad(lp + M::slot_part(s))] = x[s];
 }
 
+// Global stores and loads of the (0, E) map, in which every lane holds 2^E
+// consecutive words, routed through LDS: the global side uses the map whose
+// lanes own the lowest block bits, so that each memory instruction covers
+// consecutive words across the lanes instead of one word every 2^E.  Both
+// begin with a barrier (the workgroup's earlier LDS reads are done); the load
+// also ends with one, so that the caller may write LDS next.
+#ifndef HENTT_TS
+#define HENTT_TS 1
+#endif
+#ifndef HENTT_TL
+#define HENTT_TL 1
+#endif
+template <int B, int E, bool NT = false>
+__device__ __forceinline__ void store_global_m0(uint64_t (&x)[1 << E], uint64_t* __restrict__ dst, uint64_t* lds,
+                                                uint32_t tid) {
+#if HENTT_TS
+  using MT = RoundMap<B, E, B - E, E>;
+  __syncthreads();
+  store_lds<B, E, 0, E>(x, lds, RoundMap<B, E, 0, E>::lane_part(tid));
+  __syncthreads();
+  load_lds<B, E, B - E, E>(x, lds, MT::lane_part(tid));
+  store_global<B, E, B - E, E, NT>(x, dst, MT::lane_part(tid));
+#else
+  store_global<B, E, 0, E, NT>(x, dst, RoundMap<B, E, 0, E>::lane_part(tid));
+#endif
+}
+template <int B, int E, bool NT = false>
+__device__ __forceinline__ void load_global_m0(uint64_t (&x)[1 << E], const uint64_t* __restrict__ src, uint64_t* lds,
+                                               uint32_t tid) {
+#if HENTT_TL
+  using MT = RoundMap<B, E, B - E, E>;
+  load_global<B, E, B - E, E, NT>(x, src, MT::lane_part(tid));
+  __syncthreads();
+  store_lds<B, E, B - E, E>(x, lds, MT::lane_part(tid));
+  __syncthreads();
+  load_lds<B, E, 0, E>(x, lds, RoundMap<B, E, 0, E>::lane_part(tid));
+  __syncthreads();
+#else
+  load_global<B, E, 0, E, NT>(x, src, RoundMap<B, E, 0, E>::lane_part(tid));
+#endif
+}
+
 // Canonical reductions of forward outputs ([0, 8q)) and inverse outputs ([0, 4q)).
 template <int E> __device__ __forceinline__ void reduce_fwd(uint64_t (&x)[1 << E], const ModQ &m) {
 #pragma unroll
@@ -293,7 +335,7 @@ __global__ __launch_bounds__(1 << (LOGN - E)) void k_fwd_whole(uint64_t* __restr
   load_global<LOGN, E, F::LO, F::R>(v, p, RoundMap<LOGN, E, F::LO, F::R>::lane_part(tid));
   fwd_block_rounds<LOGN, E, F::LO, F::R>(v, LOGN, lds, tid, 0, t, m);
   reduce_fwd<E>(v, m);
-  store_global<LOGN, E, 0, E>(v, p, RoundMap<LOGN, E, 0, E>::lane_part(tid));
+  store_global_m0<LOGN, E>(v, p, lds, tid);
 }
 
 template <int LOGN, int E>
@@ -308,7 +350,7 @@ __global__ __launch_bounds__(1 << (LOGN - E)) void k_inv_whole(uint64_t* __restr
   const uint32_t tid = threadIdx.x;
   using L = InvLast<LOGN, E>;
   uint64_t v[1 << E];
-  load_global<LOGN, E, 0, E>(v, p, RoundMap<LOGN, E, 0, E>::lane_part(tid));
+  load_global_m0<LOGN, E>(v, p, lds, tid);
   inv_block_rounds<LOGN, E, 0, (LOGN < E ? LOGN : E)>(v, LOGN, lds, tid, 0, it, c);
   reduce_inv<E>(v, c.m);
   store_global<LOGN, E, L::LO, L::R>(v, p, RoundMap<LOGN, E, L::LO, L::R>::lane_part(tid));
@@ -378,7 +420,7 @@ __global__ __launch_bounds__(1 << (B - E)) void k_fwd_blocks(uint64_t *__restric
   load_global<B, E, F::LO, F::R>(v, p, RoundMap<B, E, F::LO, F::R>::lane_part(tid));
   fwd_block_rounds<B, E, F::LO, F::R>(v, LOGN, lds, tid, blockStart, t, m);
   reduce_fwd<E>(v, m);
-  store_global<B, E, 0, E>(v, p, RoundMap<B, E, 0, E>::lane_part(tid));
+  store_global_m0<B, E>(v, p, lds, tid);
 }
 
 // Block pass of the inverse transform: stages 0 .. B-1; lazy [0, 2q) output.
@@ -396,7 +438,7 @@ __global__ __launch_bounds__(1 << (B - E)) void k_inv_blocks(uint64_t *__restric
   const uint32_t tid = threadIdx.x;
   using L = InvLast<B, E>;
   uint64_t v[1 << E];
-  load_global<B, E, 0, E>(v, p, RoundMap<B, E, 0, E>::lane_part(tid));
+  load_global_m0<B, E>(v, p, lds, tid);
   inv_block_rounds<B, E, 0, E>(v, LOGN, lds, tid, blockStart, it, c);
   store_global<B, E, L::LO, L::R>(v, p, RoundMap<B, E, L::LO, L::R>::lane_part(tid));
 }
@@ -548,7 +590,6 @@ __global__ __launch_bounds__(1 << (B - E)) void k_prod(ProdArgs a, const Tw *__r
   const uint32_t tid = threadIdx.x;
   using F = FwdFirst<B, E>;
   using L = InvLast<B, E>;
-  using M0 = RoundMap<B, E, 0, E>;
   // The transform code appears once for all inputs and once for all outputs
   // (rolled loops): unrolled per polynomial it would outgrow the instruction
   // cache.  Results move between the loop's working registers and the
@@ -567,7 +608,7 @@ __global__ __launch_bounds__(1 << (B - E)) void k_prod(ProdArgs a, const Tw *__r
       if constexpr (DO_INV) reduce_for_mont<MODE, E>(v, c.m);
       else reduce_fwd<E>(v, c.m);
     } else {
-      load_global<B, E, 0, E, true>(v, a.in[p] + in_off, M0::lane_part(tid));
+      load_global_m0<B, E, true>(v, a.in[p] + in_off, lds, tid);
     }
     static_for<0, NIN>([&](auto P) {
       if (p == decltype(P)::value) {
@@ -598,7 +639,7 @@ __global__ __launch_bounds__(1 << (B - E)) void k_prod(ProdArgs a, const Tw *__r
       if constexpr (B == LOGN) reduce_inv<E>(v, c.m);
       store_global<B, E, L::LO, L::R>(v, a.out[o] + out_off, RoundMap<B, E, L::LO, L::R>::lane_part(tid));
     } else {
-      store_global<B, E, 0, E>(v, a.out[o] + out_off, M0::lane_part(tid));
+      store_global_m0<B, E>(v, a.out[o] + out_off, lds, tid);
     }
   }
 }

@@ -67,12 +67,11 @@ __global__ __launch_bounds__(1 << (LOGN - E)) void k_rs_whole(RsArgs a, const Tw
   for (int s = 0; s < (1 << E); ++s) v[s] = rs_prologue(v[s], a.qL, a.h, r, m.q);
   fwd_block_rounds<LOGN, E, F::LO, F::R>(v, LOGN, lds, tid, 0, t, m);
   reduce_fwd<E>(v, m);
-  using M0 = RoundMap<LOGN, E, 0, E>;
   uint64_t cv[1 << E];
-  load_global<LOGN, E, 0, E>(cv, a.c + (((uint64_t)b * (a.L + 1) + i) << LOGN), M0::lane_part(tid));
+  load_global_m0<LOGN, E>(cv, a.c + (((uint64_t)b * (a.L + 1) + i) << LOGN), lds, tid);
 #pragma unroll
   for (int s = 0; s < (1 << E); ++s) v[s] = rs_epilogue(cv[s], v[s], r, m);
-  store_global<LOGN, E, 0, E>(v, a.out + (((uint64_t)b * a.L + i) << LOGN), M0::lane_part(tid));
+  store_global_m0<LOGN, E>(v, a.out + (((uint64_t)b * a.L + i) << LOGN), lds, tid);
 }
 
 // Column pass (first EC forward stages) of t_i from the last limb, into out.
@@ -112,12 +111,11 @@ __global__ __launch_bounds__(1 << (B - E)) void k_rs_blocks(RsArgs a, const Tw *
   load_global<B, E, F::LO, F::R>(v, p, RoundMap<B, E, F::LO, F::R>::lane_part(tid));
   fwd_block_rounds<B, E, F::LO, F::R>(v, LOGN, lds, tid, blockStart, tw + (size_t)i * 2 * (1u << LOGN), m);
   reduce_fwd<E>(v, m);
-  using M0 = RoundMap<B, E, 0, E>;
   uint64_t cv[1 << E];
-  load_global<B, E, 0, E>(cv, a.c + (((uint64_t)b * (a.L + 1) + i) << LOGN) + blockStart, M0::lane_part(tid));
+  load_global_m0<B, E>(cv, a.c + (((uint64_t)b * (a.L + 1) + i) << LOGN) + blockStart, lds, tid);
 #pragma unroll
   for (int s = 0; s < (1 << E); ++s) v[s] = rs_epilogue(cv[s], v[s], r, m);
-  store_global<B, E, 0, E>(v, p, M0::lane_part(tid));
+  store_global_m0<B, E>(v, p, lds, tid);
 }
 
 // Coefficient-domain rescale: element-wise, tiles of 2048 words.
