@@ -231,6 +231,37 @@ def test_relin(gpu, log_n, l):
     assert np.array_equal(host(cd), c)
 
 
+def test_rescale_bench_shape_sampled(gpu):
+    """Rescale at the benchmarked shape (64 polynomials of N = 2^16, 24 -> 23
+    limbs, NTT domain, one call over the whole batch as the benchmark makes
+    it): sampled batch entries, every limb and coefficient, against the oracle."""
+    import paper_2109_14704_amd as H
+    print("case rescale 64 x 24 x 2^16", flush=True)
+    mods = workloads.moduli("ct_tensor")
+    rng = np.random.default_rng(801)
+    x = rand_limbs(rng, (64, 24, 1 << 16), mods)
+    t = H.Tables(16, mods)
+    got = host(H.rescale(t, dev(x, gpu), ntt=True))
+    for b in (0, 37, 63):
+        assert np.array_equal(got[b:b + 1], oracle.batch_rescale_ntt(x[b:b + 1], mods)), b
+
+
+def test_relin_bench_shape_sampled(gpu):
+    """Relinearization at the routine benchmark's shape (32 ciphertexts of
+    N = 2^15 at 8 primes plus P, one call over the batch): sampled batch
+    entries, every limb and coefficient, against the oracle."""
+    import paper_2109_14704_amd as H
+    print("case relin 32 x 8 x 2^15", flush=True)
+    mods = workloads.moduli("ct_tensor")[:9]
+    rng = np.random.default_rng(802)
+    c = rand_limbs(rng, (32, 3, 8, 1 << 15), mods[:8])
+    ksk = rand_limbs(rng, (8, 2, 9, 1 << 15), mods)
+    t = H.Tables(15, mods)
+    got = host(H.relin(t, dev(c, gpu), dev(ksk, gpu)))
+    for b in (0, 19, 31):
+        assert np.array_equal(got[b:b + 1], oracle.relin(c[b:b + 1], ksk, mods)), b
+
+
 def test_plain4096_workload(gpu):
     """Workload 1 at full size: 8 polys fwd + inv, one polymul vs schoolbook."""
     import paper_2109_14704_amd as H
