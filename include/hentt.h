@@ -114,7 +114,8 @@ int hentt_rescale(const hentt_tables *t, const uint64_t *c, uint64_t *out, uint3
  * domain: C (m x n) += A (m x k) * B (k x n) where every matrix element is a
  * ciphertext and every element product the Mul tensor of section II-A
  * (c0 d0, c0 d1 + c1 d0, c1 d1), accumulated over k with one modular
- * reduction per multiply-add (mad_mod, section III-A-1).
+ * reduction per output term of every element product (the middle term's two
+ * products summed first: mad_mod, section III-A-1).
  * A [m][k][2][limbs][N], B [k][n][2][limbs][N], C [m][n][3][limbs][N] with
  * limbs and N those of t; canonical inputs, canonical C.  C is updated in
  * place and must not overlap A or B.  HENTT_EINVAL for null pointers, a zero
@@ -128,8 +129,9 @@ int hentt_ct_matmul(const hentt_tables *t, const uint64_t *A, const uint64_t *B,
  * by the special prime P (l >= 1).  c [batch][3][l][N] (the Mul tensor),
  * ksk [l][2][l + 1][N] (digit j, component s, prime: the key-switching key,
  * caller-owned), out [batch][2][l][N]; canonical inputs and outputs.  out must
- * not overlap c or ksk (HENTT_EINVAL).  The last limb's rescale constants are
- * made on the first call (a synchronous upload); later calls only enqueue. */
+ * not overlap c or ksk (HENTT_EINVAL).  The level's rescale and key-switching
+ * constants are made on its first call (a synchronous upload); later calls
+ * only enqueue. */
 int hentt_relin(const hentt_tables *t, const uint64_t *c, const uint64_t *ksk, uint64_t *out, uint32_t batch,
                 void *stream);
 
