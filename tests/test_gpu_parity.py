@@ -262,6 +262,58 @@ def test_relin_bench_shape_sampled(gpu):
         assert np.array_equal(got[b:b + 1], oracle.relin(c[b:b + 1], ksk, mods)), b
 
 
+TOP = [q for q in CHAIN if q.bit_length() == 60]  # the largest primes (q < 2^60): tightest lazy ranges
+
+
+def extremes(rng, shape, mods):
+    """Half the words at q - 1, the rest uniform: the largest operands the
+    products and their lazy ranges must take."""
+    x = rand_limbs(rng, shape, mods)
+    for l, q in enumerate(mods):
+        sl = x[..., l, :]
+        sl[..., ::2] = q - 1
+    return x
+
+
+@pytest.mark.parametrize("log_n", [12, 15, 16])
+def test_products_at_largest_primes_and_operands(gpu, log_n):
+    """Fused and NTT-domain products (Montgomery ahead of the inverse
+    transform, Barrett otherwise) with 60-bit primes and operands at q - 1."""
+    import paper_2109_14704_amd as H
+    print("case extremes products log_n=%d" % log_n, flush=True)
+    mods = TOP[:2]
+    rng = np.random.default_rng(900 + log_n)
+    t = H.Tables(log_n, mods)
+    a, b = extremes(rng, (2, 2, 1 << log_n), mods), extremes(rng, (2, 2, 1 << log_n), mods)
+    assert np.array_equal(host(H.polymul(t, dev(a, gpu), dev(b, gpu))), oracle.batch_polymul(a, b, mods))
+    c, d = extremes(rng, (2, 2, 2, 1 << log_n), mods), extremes(rng, (2, 2, 2, 1 << log_n), mods)
+    want_ntt = oracle.batch_tensor(c, d, mods)                  # NTT-domain in and out: plain products
+    assert np.array_equal(host(H.ct_tensor(t, dev(c, gpu), dev(d, gpu), in_ntt=True, out_ntt=True)), want_ntt)
+    want = oracle.batch_ntt(want_ntt, mods, -1)                 # NTT-domain in, coefficient out: Montgomery
+    assert np.array_equal(host(H.ct_tensor(t, dev(c, gpu), dev(d, gpu), in_ntt=True)), want)
+
+
+def test_relin_and_matmul_at_largest_primes_and_operands(gpu):
+    """Key switch (Montgomery accumulation) and matMul (both accumulation
+    forms) with 60-bit primes and operands at q - 1."""
+    import paper_2109_14704_amd as H
+    mods = TOP[:3]
+    rng = np.random.default_rng(903)
+    t = H.Tables(13, mods)
+    c = extremes(rng, (2, 3, 2, 1 << 13), mods[:2])
+    ksk = extremes(rng, (2, 2, 3, 1 << 13), mods)
+    assert np.array_equal(host(H.relin(t, dev(c, gpu), dev(ksk, gpu))), oracle.relin(c, ksk, mods))
+    m2 = TOP[:2]
+    t2 = H.Tables(12, m2)
+    for k in (1, 4):
+        A = extremes(rng, (2, k, 2, 2, 1 << 12), m2)
+        B = extremes(rng, (k, 3, 2, 2, 1 << 12), m2)
+        C = extremes(rng, (2, 3, 3, 2, 1 << 12), m2)
+        Cd = dev(C, gpu)
+        H.ct_matmul(t2, dev(A, gpu), dev(B, gpu), Cd)
+        assert np.array_equal(host(Cd), oracle.ct_matmul(A, B, C, m2)), k
+
+
 def test_plain4096_workload(gpu):
     """Workload 1 at full size: 8 polys fwd + inv, one polymul vs schoolbook."""
     import paper_2109_14704_amd as H
