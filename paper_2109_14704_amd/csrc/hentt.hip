@@ -282,7 +282,7 @@ void launch_fwd(const hentt_tables *t, uint64_t *x, uint32_t batch, hipStream_t 
   if constexpr (P::WHOLE) {
     { LaunchTimer lt_("k_fwd_whole", LOGN, st); hipLaunchKernelGGL((k_fwd_whole<LOGN, 4>), dim3(units), dim3(1 << (LOGN - 4)), 0, st, x, tw, lc, batch, L); }
   } else {
-    { LaunchTimer lt_("k_cols_fwd", LOGN, st); hipLaunchKernelGGL((k_cols<LOGN, P::EC, false>), dim3(units * ((1u << (LOGN - P::EC)) / 256)), dim3(256), 0, st,
+    { LaunchTimer lt_("k_cols_fwd", LOGN, st); hipLaunchKernelGGL((k_cols<LOGN, P::EC, false>), dim3(units * ((1u << (LOGN - P::EC)) / (256 * ColCpl<P::EC>::value))), dim3(256), 0, st,
                        col_args(x, (uint64_t)L << LOGN), tw, lc, batch, L); }
     { LaunchTimer lt_("k_fwd_blocks", LOGN, st); hipLaunchKernelGGL((k_fwd_blocks<LOGN, P::B, 4>), dim3(units << (LOGN - P::B)), dim3(1 << (P::B - 4)), 0, st, x,
                        tw, lc, batch, L); }
@@ -301,7 +301,7 @@ void launch_inv(const hentt_tables *t, uint64_t *x, uint32_t batch, hipStream_t 
   } else {
     { LaunchTimer lt_("k_inv_blocks", LOGN, st); hipLaunchKernelGGL((k_inv_blocks<LOGN, P::B, 4>), dim3(units << (LOGN - P::B)), dim3(1 << (P::B - 4)), 0, st, x,
                        tw, lc, batch, L); }
-    { LaunchTimer lt_("k_cols_inv", LOGN, st); hipLaunchKernelGGL((k_cols<LOGN, P::EC, true>), dim3(units * ((1u << (LOGN - P::EC)) / 256)), dim3(256), 0, st,
+    { LaunchTimer lt_("k_cols_inv", LOGN, st); hipLaunchKernelGGL((k_cols<LOGN, P::EC, true>), dim3(units * ((1u << (LOGN - P::EC)) / (256 * ColCpl<P::EC>::value))), dim3(256), 0, st,
                        col_args(x, (uint64_t)L << LOGN), tw, lc, batch, L); }
   }
 }
@@ -360,7 +360,7 @@ void launch_prod(const hentt_tables *t, const ProdArgs &pa, uint32_t batch, bool
       ca.src_sb = pa.in_sb;
       ca.dst_sb = NL;
       pb.in_sb = NL;
-      { LaunchTimer lt_("k_cols_fwd", LOGN, st); hipLaunchKernelGGL((k_cols<LOGN, EC, false>), dim3(NIN * units * ((1u << (LOGN - EC)) / 256)), dim3(256), 0, st,
+      { LaunchTimer lt_("k_cols_fwd", LOGN, st); hipLaunchKernelGGL((k_cols<LOGN, EC, false>), dim3(NIN * units * ((1u << (LOGN - EC)) / (256 * ColCpl<EC>::value))), dim3(256), 0, st,
                          ca, tw, lc, batch, L); }
     }
     const dim3 g(units << (LOGN - B)), blk(1 << (B - PE));
@@ -371,7 +371,7 @@ void launch_prod(const hentt_tables *t, const ProdArgs &pa, uint32_t batch, bool
       ColArgs ca{};
       for (int o = 0; o < NOUT; ++o) ca.src[o] = ca.dst[o] = pa.out[o];
       ca.src_sb = ca.dst_sb = pa.out_sb;
-      { LaunchTimer lt_("k_cols_inv", LOGN, st); hipLaunchKernelGGL((k_cols<LOGN, EC, true>), dim3(NOUT * units * ((1u << (LOGN - EC)) / 256)), dim3(256), 0, st,
+      { LaunchTimer lt_("k_cols_inv", LOGN, st); hipLaunchKernelGGL((k_cols<LOGN, EC, true>), dim3(NOUT * units * ((1u << (LOGN - EC)) / (256 * ColCpl<EC>::value))), dim3(256), 0, st,
                          ca, tw, lc, batch, L); }
     }
   }
@@ -512,7 +512,7 @@ void launch_naive_stages(const hentt_tables *t, uint64_t *x, uint64_t units, uin
 template <int E> void launch_staged15(const hentt_tables *t, uint64_t *x, uint32_t batch, hipStream_t st) {
   const uint32_t L = t->limbs, units = batch * L;
   const char *name = E == 2 ? "k_fwd_blocks_r4" : E == 3 ? "k_fwd_blocks_r8" : "k_fwd_blocks_r16";
-  { LaunchTimer lt_("k_cols_fwd_r8", 15, st); hipLaunchKernelGGL((k_cols<15, 3, false>), dim3(units * ((1u << 12) / 256)), dim3(256), 0, st, col_args(x, (uint64_t)L << 15), t->s->d_tw, t->s->d_lc, batch, L); }
+  { LaunchTimer lt_("k_cols_fwd_r8", 15, st); hipLaunchKernelGGL((k_cols<15, 3, false>), dim3(units * ((1u << 12) / (256 * ColCpl<3>::value))), dim3(256), 0, st, col_args(x, (uint64_t)L << 15), t->s->d_tw, t->s->d_lc, batch, L); }
   { LaunchTimer lt_(name, 15, st); hipLaunchKernelGGL((k_fwd_blocks<15, 12, E>), dim3(units << 3), dim3(1 << (12 - E)), 0, st, x, t->s->d_tw, t->s->d_lc, batch, L); }
 }
 

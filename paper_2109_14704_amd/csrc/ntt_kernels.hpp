@@ -385,10 +385,49 @@ __device__ __forceinline__ void col_pass(const uint64_t *src, uint64_t *dst, uin
   store_global<LOGN, E, LO, E, true>(v, dst, col);
 }
 
+// Columns per lane: two neighbouring columns (16-byte accesses) for passes of
+// up to 16 words per lane; at 32 words per lane the doubled registers cost
+// more than the wider accesses gain (measured: column passes of 2^17
+// transforms 12% faster, of the 2^15 and 2^16 products 6-10% slower).
+template <int E> struct ColCpl { static constexpr int value = E <= 4 ? 2 : 1; };
+typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
+// Two neighbouring columns per lane: 16-byte accesses.
+template <int LOGN, int E, bool INV>
+__device__ __forceinline__ void col_pass2(const uint64_t *src, uint64_t *dst, uint32_t col, const Tw *t,
+                                          const LimbConst &c) {
+  constexpr int LO = LOGN - E;
+  uint64_t v0[1 << E], v1[1 << E];
+#pragma unroll
+  for (int s = 0; s < (1 << E); ++s) {
+    const HENTT_GLOBAL u64x2 *p = (const HENTT_GLOBAL u64x2 *)((const HENTT_GLOBAL char *)src + ((col + (s << LO)) << 3));
+    const u64x2 w = __builtin_nontemporal_load(p);
+    v0[s] = w.x;
+    v1[s] = w.y;
+  }
+  if constexpr (!INV) {
+    fwd_round<LOGN, E, LO, E>(v0, LOGN, 0, col, t, c.m);
+    fwd_round<LOGN, E, LO, E>(v1, LOGN, 0, col, t, c.m);
+  } else {
+    inv_round<LOGN, E, LO, E>(v0, LOGN, 0, col, t, c);
+    inv_round<LOGN, E, LO, E>(v1, LOGN, 0, col, t, c);
+    reduce_inv<E>(v0, c.m);
+    reduce_inv<E>(v1, c.m);
+  }
+#pragma unroll
+  for (int s = 0; s < (1 << E); ++s) {
+    HENTT_GLOBAL u64x2 *p = (HENTT_GLOBAL u64x2 *)((HENTT_GLOBAL char *)dst + ((col + (s << LO)) << 3));
+    u64x2 w;
+    w.x = v0[s];
+    w.y = v1[s];
+    __builtin_nontemporal_store(w, p);
+  }
+}
+
 template <int LOGN, int E, bool INV>
 __global__ __launch_bounds__(256) void k_cols(ColArgs a, const Tw *__restrict__ tw, const LimbConst *__restrict__ lc,
                                               uint32_t batch, uint32_t limbs) {
-  constexpr uint32_t tiles = (1u << (LOGN - E)) / 256;
+  constexpr uint32_t CPL = ColCpl<E>::value;
+  constexpr uint32_t tiles = (1u << (LOGN - E)) / (256 * CPL);
   const uint32_t units = batch * limbs;
   const uint32_t tile = blockIdx.x % tiles;
   const uint32_t r = blockIdx.x / tiles;
@@ -398,7 +437,9 @@ __global__ __launch_bounds__(256) void k_cols(ColArgs a, const Tw *__restrict__ 
   const uint64_t off = (uint64_t)limb << LOGN;
   const uint64_t *src = a.src[comp] + (uint64_t)b * a.src_sb + off;
   uint64_t *dst = a.dst[comp] + (uint64_t)b * a.dst_sb + off;
-  col_pass<LOGN, E, INV>(src, dst, tile * 256 + threadIdx.x, tw + ((size_t)limb * 2 + (INV ? 1 : 0)) * (1u << LOGN), c);
+  const Tw *t = tw + ((size_t)limb * 2 + (INV ? 1 : 0)) * (1u << LOGN);
+  if constexpr (CPL == 2) col_pass2<LOGN, E, INV>(src, dst, tile * 512 + 2 * threadIdx.x, t, c);
+  else col_pass<LOGN, E, INV>(src, dst, tile * 256 + threadIdx.x, t, c);
 }
 
 // Block pass of the forward transform: stages LOGN-B .. LOGN-1 on contiguous
