@@ -256,7 +256,8 @@ VALU_BFLY = 21     # Harvey/Shoup butterfly: 9 32-bit multiplies + 12 adds, comp
 VALU_PROD = 19     # Montgomery product a b R^-1 mod q: 128-bit product, low product by -q^-1, high product by q
 VALU_TENSOR = 68   # c0d0, c1d1 (2 x 19) + c0d1 + c1d0 with one Montgomery reduction (30)
 VALU_RS_EPI = 17   # rescale epilogue: Shoup product by qL^-1 (9 + adds) and a reduction from [0, 4q)
-VALU_MAC = 83      # one matMul product term: the tensor's Montgomery products (68) and three lazy additions (5 each)
+VALU_MAC = 83      # one matMul product term, k >= 3: the tensor's Montgomery products (68), three lazy additions (5 each)
+VALU_MAC_B = 121   # one matMul product term, k <= 2: the tensor's three outputs accumulated with Barrett mad_mod
 VALU_KS_MAC = 24   # key switch, per digit word and key component: Montgomery product (19), lazy addition (5)
 VALU_KS_FIN = 20   # key switch, per output word: Shoup product by R mod q (12), reduction from [0, 4q) (8)
 VALU_KS_FIN_C = 38 # the same plus P c_s: a second Shoup product, an addition, a reduction from [0, 8q)
@@ -439,7 +440,8 @@ def bench_matmul(args):
     IV-E): C += A*B with ciphertext elements of N = 8192 over 4 limbs, NTT
     domain, 100x100x1 and 10x9x8 (m x n x k).  Value: element ciphertext
     products per second on 100x100x1.  Roofline against the compulsory bytes
-    (A and B once, C read and written) and VALU_MAC ops per product term."""
+    (A and B once, C read and written) and VALU_MAC ops per product term
+    (VALU_MAC_B for k <= 2, which the kernel accumulates with Barrett)."""
     import torch
     import workloads
     import paper_2109_14704_amd as H
@@ -472,7 +474,7 @@ def bench_matmul(args):
         torch.cuda.synchronize()
         ms = a.elapsed_time(b) / reps
         nbytes = 8.0 * L * n_ * (2 * m * k + 2 * k * n + 6 * m * n)
-        ops = float(VALU_MAC) * m * n * k * L * n_
+        ops = float(VALU_MAC if k >= 3 else VALU_MAC_B) * m * n * k * L * n_
         t_hbm, t_alu = nbytes / (R.HBM_PEAK_GBS * 1e9), ops / (R.VALU_PEAK_TOPS * 1e12)
         if t_hbm >= t_alu:
             rl = {"bound": "hbm", "achieved": round(nbytes / ms / 1e6, 1), "peak": R.HBM_PEAK_GBS, "unit": "GB/s",
