@@ -74,7 +74,7 @@ def setup(name, torch, H, grid_arg=0):
         info = {"workload": "ckks_level", "N": n, "limbs": L, "polys_per_operand": polys,
                 "ops": "fwd(A), fwd(B), dyadic, inv (fused polymul)"}
         return dict(step=step, per_poly=per_poly_step, coeffs=3 * polys * L * n, t=t, info=info, w=w,
-                    cpu=lambda k: cpu_ckks(w, k))
+                    cpu=lambda k: cpu_ckks(w, k), cpu1=lambda k: cpu_ckks_1core(w, k))
     if name == "ct_tensor":
         w = workloads.ct_tensor()
         t = H.Tables(w["log_n"], w["moduli"])
@@ -185,6 +185,16 @@ def cpu_ckks(w, k):
     return dt, 3 * a.size
 
 
+def cpu_ckks_1core(w, k):
+    """The CKKS-level oracle on one host thread."""
+    import oracle
+    a, b = w["a"][:k], w["b"][:k]
+    t0 = time.perf_counter()
+    oracle.batch_polymul(a, b, w["moduli"], threads=1)
+    dt = time.perf_counter() - t0
+    return dt, 3 * a.size
+
+
 def cpu_tensor(w, k):
     import oracle
     c, d = w["c"][:k], w["d"][:k]
@@ -227,25 +237,27 @@ def cpu_plain(w, k):
     return dt, 2 * x.size * k
 
 
-def cpu_baseline(s, target_s):
+def cpu_baseline(s, target_s, one_core=False):
     import oracle
     k, limit = 1, len(s["w"].get("a", s["w"].get("c", s["w"].get("x"))))
     if s["info"]["workload"] == "uneven":
         k = 4
-    dt, coeffs = s["cpu"](k)
+    cpu = s["cpu1"] if one_core else s["cpu"]
+    dt, coeffs = cpu(k)
     while dt < target_s / 2 and k < limit:      # grow the sample to about the target time
         k = min(limit, max(k + 1, int(k * target_s / max(dt, 1e-3))))
-        dt, coeffs = s["cpu"](k)
+        dt, coeffs = cpu(k)
     reps = 1
     if dt < target_s / 2:                       # the whole workload is short: repeat it
         reps = max(1, int(round(target_s / max(dt, 1e-3))))
         dt, coeffs = 0.0, 0
         for _ in range(reps):
-            d1, c1 = s["cpu"](k)
+            d1, c1 = cpu(k)
             dt, coeffs = dt + d1, coeffs + c1
-    return {"value": coeffs / dt / 1e9, "unit": "Gcoeff/s", "cores": oracle.max_threads(), "kind": "oracle",
-            "sample": "%d batch entr%s of the same workload%s (radix-2 oracle, OpenMP over (batch, limb)), %.1f s"
-                      % (k, "y" if k == 1 else "ies", ", %d times" % reps if reps > 1 else "", dt)}
+    return {"value": coeffs / dt / 1e9, "unit": "Gcoeff/s", "cores": 1 if one_core else oracle.max_threads(), "kind": "oracle",
+            "sample": "%d batch entr%s of the same workload%s (radix-2 oracle, %s), %.1f s"
+                      % (k, "y" if k == 1 else "ies", ", %d times" % reps if reps > 1 else "",
+                         "one thread" if one_core else "OpenMP over (batch, limb)", dt)}
 
 
 # ---------------------------------------------------------------- roofline
@@ -731,6 +743,8 @@ def main():
     if not args.no_cpu:
         print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(s, args.cpu_seconds)
+        if "cpu1" in s:                          # the same oracle on one host thread, a shorter sample
+            result["cpu_baseline_1core"] = cpu_baseline(s, args.cpu_seconds / 3, one_core=True)
     print(json.dumps(result), flush=True)
 
 
