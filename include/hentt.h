@@ -45,6 +45,8 @@ extern "C" {
 #define HENTT_ENOMEM (-3)    /* host or device allocation failed */
 #define HENTT_EHIP (-4)      /* a HIP runtime call failed; see hentt_last_hip_error() */
 #define HENTT_ETIMEOUT (-5)  /* a persistent batch tile gave up waiting (reported by hentt_batch_plan_status) */
+#define HENTT_EBUSY (-6)     /* a batch plan still has live graphs (hentt_batch_plan_set_grid / _destroy) */
+#define HENTT_ENONCANON (-7) /* hentt_check_canonical found input words outside [0, q) */
 
 #define HENTT_LOG_N_MIN 6
 #define HENTT_LOG_N_MAX 17
@@ -91,6 +93,19 @@ int hentt_tables_device_ptrs(const hentt_tables *t, const uint64_t **fwd, const 
 /* The library's psi for (q, N): smallest primitive 2N-th root of unity mod q.
  * Host-only helper, no device work. */
 int hentt_psi(uint64_t q, uint32_t log_n, uint64_t *psi);
+
+/* Debug check of the input precondition that every compute call assumes and
+ * none checks: the words of x[batch][limbs][N] are canonical residues,
+ * x[b][l][i] < q_l (the input range of Algorithm 1, whose last round brings
+ * outputs back into [0, q); section III-B).  Enqueues a check kernel on
+ * `stream` and then WAITS for the stream (debug use, not for the hot path).
+ * Returns HENTT_OK when every word is canonical, HENTT_ENONCANON otherwise;
+ * bad_words (optional) receives the number of non-canonical words and
+ * first_bad (optional) the smallest flat word index of one (~0 if none).
+ * HENTT_EINVAL for null x or t, batch 0, or more than 2^31 - 1 tiles of 2048
+ * words. */
+int hentt_check_canonical(const hentt_tables *t, const uint64_t *x, uint32_t batch, uint64_t *bad_words,
+                          uint64_t *first_bad, void *stream);
 
 /* Forward negacyclic NTT in place: x[batch][limbs][N], natural order ->
  * bit-reversed NTT domain (section II-B). */
@@ -165,13 +180,16 @@ int hentt_ntt_fwd_variant(const hentt_tables *t, uint64_t *x, uint32_t batch, in
 int hentt_ntt_inv(const hentt_tables *t, uint64_t *x, uint32_t batch, void *stream);
 
 /* Element-wise (dyadic) product out = a (.) b mod q_l over [batch][limbs][N]
- * (section II-B).  out may alias a or b exactly (not partially). */
+ * (section II-B).  out may alias a or b exactly; a partial overlap returns
+ * HENTT_EINVAL. */
 int hentt_dyadic_mul(const hentt_tables *t, const uint64_t *a, const uint64_t *b, uint64_t *out,
                      uint32_t batch, void *stream);
 
 /* Negacyclic products out = INTT(NTT(a) (.) NTT(b)) of coefficient-domain
  * a, b over [batch][limbs][N] (section II-B), fused so that the NTT-domain
- * values never leave the chip.  out must not overlap a or b. */
+ * values never leave the chip.  out must not overlap a or b (HENTT_EINVAL).
+ * For N > 2^12 the forward column pass writes a workspace of 2 batch limbs N
+ * words taken from the library's pool (allocated on first need, reused). */
 int hentt_polymul(const hentt_tables *t, const uint64_t *a, const uint64_t *b, uint64_t *out, uint32_t batch,
                   void *stream);
 
@@ -179,7 +197,9 @@ int hentt_polymul(const hentt_tables *t, const uint64_t *a, const uint64_t *b, u
  * out [batch][3][limbs][N] = (c0 d0, c0 d1 + c1 d0, c1 d1) per limb, the middle
  * term reduced once (mad_mod).  flags: HENTT_IN_COEFF | HENTT_IN_NTT combined
  * with HENTT_OUT_COEFF | HENTT_OUT_NTT.  c and d are not modified; out must
- * not overlap them. */
+ * not overlap them (HENTT_EINVAL).  With coefficient-domain inputs and
+ * N > 2^12 the forward column pass writes a workspace of 4 batch limbs N
+ * words from the library's pool. */
 int hentt_ct_tensor(const hentt_tables *t, const uint64_t *c, const uint64_t *d, uint64_t *out, uint32_t batch,
                     uint32_t flags, void *stream);
 
@@ -197,17 +217,31 @@ typedef struct {
  * batch and RNS limbs give independent transforms).  jobs is a HOST array; it
  * is read before the call returns.  The first call with a given job list
  * builds a plan (tile list on the device, synchronous) and caches it (up to
- * 16 plans, keyed by pointers, shapes and direction); later calls only
- * enqueue.  Jobs with N < 2^12 run as ordinary launches in the same call. */
+ * 16 plans, keyed by the data pointers, the table storages, N, limb counts,
+ * batch sizes and direction); later calls only enqueue.  A cached plan holds
+ * a reference on every table storage it uses; hentt_tables_destroy evicts
+ * the plans of the destroyed table's storage.  Jobs with N < 2^12 run as
+ * ordinary launches in the same call. */
 int hentt_ntt_batch(const hentt_job *jobs, uint32_t njobs, int dir, void *stream);
+
+/* Status of the last hentt_ntt_batch call with this job list and direction:
+ * waits for it, then HENTT_ETIMEOUT if one of its pass-2 tiles gave up
+ * waiting (bounded spin) or a queue went unserved, else HENTT_OK.
+ * HENTT_EINVAL if no cached plan matches. */
+int hentt_ntt_batch_status(const hentt_job *jobs, uint32_t njobs, int dir);
 
 /* Explicit plans for the same persistent launch (for autotuning and graphs).
  * create: validates the jobs and uploads the tile list (synchronous).
- * set_grid: number of persistent workgroups (0 = 4 per compute unit).
+ * set_grid: number of persistent workgroups (0 = 2 per compute unit);
+ *   HENTT_EBUSY while graphs captured from the plan exist (they hold the
+ *   old launch shape).
  * run: enqueues a counter reset kernel and the persistent kernel on stream.
- * status: waits for the last run; HENTT_ETIMEOUT if a pass-2 tile gave up
- * waiting for its pass-1 tiles (bounded spin), else HENTT_OK.
- * The job data stay owned by the caller and must outlive every run. */
+ * status: waits for the last run or graph replay; HENTT_ETIMEOUT if a pass-2
+ *   tile gave up waiting for its pass-1 tiles (bounded spin) or a queue went
+ *   unserved, else HENTT_OK.
+ * destroy: HENTT_EBUSY while graphs captured from the plan exist.
+ * The plan holds a reference on every table storage it uses.  The job data
+ * stay owned by the caller and must outlive every run. */
 typedef struct hentt_batch_plan hentt_batch_plan;
 int hentt_batch_plan_create(const hentt_job *jobs, uint32_t njobs, int dir, hentt_batch_plan **out);
 int hentt_batch_plan_set_grid(hentt_batch_plan *p, uint32_t workgroups);
@@ -218,11 +252,22 @@ int hentt_batch_plan_destroy(hentt_batch_plan *p);
 
 /* A plan's launch sequence captured once into a hipGraph (on a private
  * stream; the counter reset is a kernel, not a memset node) and replayed with
- * hentt_graph_launch on any stream. */
+ * hentt_graph_launch on any stream; each replay records the plan's
+ * completion event, so hentt_batch_plan_status reports on the last replay.
+ * Destroy the graphs before the plan. */
 typedef struct hentt_graph hentt_graph;
 int hentt_batch_graph_create(hentt_batch_plan *p, hentt_graph **out);
 int hentt_graph_launch(hentt_graph *g, void *stream);
 int hentt_graph_destroy(hentt_graph *g);
+
+/* Workspace pool (the memory cache of section III-C-1): device buffers for
+ * the column passes of two-pass products, rescale and relinearization are
+ * kept after use and reused by later calls on the same device and stream.
+ * hentt_pool_bytes reports the bytes the pool holds; hentt_pool_trim waits
+ * for the streams of the idle buffers and frees them (buffers of calls still
+ * being enqueued by other threads are kept). */
+int hentt_pool_bytes(uint64_t *bytes);
+int hentt_pool_trim(void);
 
 /* Kernel timing for benchmarks.  While enabled, every kernel the library
  * launches is bracketed by HIP events recorded on the launching stream.

@@ -13,7 +13,8 @@ import torch
 
 __all__ = ["HenttError", "Tables", "ntt_fwd", "ntt_inv", "dyadic_mul", "polymul", "ct_tensor", "ntt_batch",
            "psi", "lib", "LIB_PATH", "prof_enable", "prof_read", "BatchPlan", "stage_split", "ntt_fwd_variant",
-           "rescale", "ct_matmul", "relin"]
+           "rescale", "ct_matmul", "relin", "check_canonical", "ntt_batch_status", "pool_bytes", "pool_trim",
+           "NonCanonicalError"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("HENTT_LIB") or os.path.join(_HERE, "libhentt.so")  # HENTT_LIB: alternative build
@@ -27,6 +28,10 @@ _U64 = ctypes.c_uint64
 
 class HenttError(RuntimeError):
     pass
+
+
+class NonCanonicalError(HenttError):
+    """Raised by check_canonical: input words outside [0, q)."""
 
 
 class _Job(ctypes.Structure):
@@ -60,6 +65,10 @@ def lib():
             "hentt_polymul": [_VP, _VP, _VP, _VP, _U32, _VP],
             "hentt_ct_tensor": [_VP, _VP, _VP, _VP, _U32, _U32, _VP],
             "hentt_ntt_batch": [ctypes.POINTER(_Job), _U32, ctypes.c_int, _VP],
+            "hentt_ntt_batch_status": [ctypes.POINTER(_Job), _U32, ctypes.c_int],
+            "hentt_check_canonical": [_VP, _VP, _U32, ctypes.POINTER(_U64), ctypes.POINTER(_U64), _VP],
+            "hentt_pool_bytes": [ctypes.POINTER(_U64)],
+            "hentt_pool_trim": [],
             "hentt_last_hip_error": [],
             "hentt_batch_plan_create": [ctypes.POINTER(_Job), _U32, ctypes.c_int, ctypes.POINTER(_VP)],
             "hentt_batch_plan_set_grid": [_VP, _U32],
@@ -199,6 +208,30 @@ def _batch_of(tables, x, per_item=1, name="x"):
     if b * per_item * tables.limbs * tables.n != x.numel() or b == 0:
         raise HenttError("%s: size is not a whole number of items" % name)
     return b
+
+
+def check_canonical(tables, x, stream=None):
+    """Debug check that every word of x[..., limbs, N] is below its limb's
+    modulus.  Synchronises the stream.  Returns None, or raises
+    NonCanonicalError naming the count and the first offending flat index."""
+    bad, first = _U64(), _U64()
+    rc = lib().hentt_check_canonical(tables.handle, _words(x, "x"), _batch_of(tables, x), ctypes.byref(bad),
+                                     ctypes.byref(first), _stream(stream))
+    if rc == -7:
+        raise NonCanonicalError("%d words outside [0, q); first at flat index %d" % (bad.value, first.value))
+    _check(rc, "hentt_check_canonical")
+
+
+def pool_bytes():
+    """Device bytes held by the library's workspace pool."""
+    n = _U64()
+    _check(lib().hentt_pool_bytes(ctypes.byref(n)), "hentt_pool_bytes")
+    return n.value
+
+
+def pool_trim():
+    """Free the pool's idle workspace buffers (after their streams finish)."""
+    _check(lib().hentt_pool_trim(), "hentt_pool_trim")
 
 
 def ntt_fwd(tables, x, stream=None):
@@ -347,8 +380,8 @@ class BatchPlan:
         return {"units": u.value, "tiles": t.value, "grid": g.value}
 
     def set_grid(self, workgroups):
+        self.drop_graph()              # a captured graph holds the old launch shape
         _check(lib().hentt_batch_plan_set_grid(self._h, int(workgroups)), "plan_set_grid")
-        self.drop_graph()
 
     def run(self, stream=None):
         _check(lib().hentt_batch_plan_run(self._h, _stream(stream)), "plan_run")
@@ -392,3 +425,10 @@ def ntt_batch(jobs, direction, stream=None):
     with x [batch, limbs, N] for that tables' N; direction +1 or -1."""
     arr = _job_array(jobs)
     _check(lib().hentt_ntt_batch(arr, len(jobs), int(direction), _stream(stream)), "hentt_ntt_batch")
+
+
+def ntt_batch_status(jobs, direction):
+    """Wait for the last ntt_batch call with this job list and direction and
+    raise if one of its tiles gave up waiting (results incomplete)."""
+    arr = _job_array(jobs)
+    _check(lib().hentt_ntt_batch_status(arr, len(jobs), int(direction)), "hentt_ntt_batch_status")

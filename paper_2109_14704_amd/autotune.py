@@ -1,10 +1,22 @@
 """Autotuner for launch parameters, with a JSON cache.
 
-Candidates are timed only after they reproduce the reference candidate's
-output words exactly (parity gate).  Tuned knob: the number of persistent
-workgroups of an uneven-batch plan.  The cache is keyed by device
-architecture, a digest of the kernel sources (a tuned choice is void once
-the kernels change) and a signature of the plan (units, tiles).
+Parity gate: the default candidate's outputs are computed first and, when a
+`check` function is given (the GPU tests pass one that compares with the
+CPU oracle), verified by it; every other candidate is timed only after its
+outputs equal the default's word for word, and a candidate that differs is
+never chosen.  The default configurations are the ones the GPU parity tests
+compare with the oracle, so a cached choice is always a configuration whose
+results equal an oracle-checked result.
+
+Tuned knobs:
+  * persistent_grid: the number of persistent workgroups of an uneven-batch
+    plan;
+  * kernel_config: the compiled kernel instance (stage split, words per
+    lane, columns per lane) of a transform or fused product at one
+    (N, limbs, batch) shape class.
+
+The cache is keyed by device architecture, a digest of the kernel sources
+(a tuned choice is void once the kernels change) and the tuned shape.
 """
 import json
 import os
@@ -16,6 +28,14 @@ from .roofline import source_digest
 _CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
 
 
+class ParityError(RuntimeError):
+    """The default candidate's outputs failed the caller's check."""
+
+
+def cache_path():
+    return os.environ.get("HENTT_TUNE_CACHE", _CACHE)
+
+
 def _arch():
     try:
         return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
@@ -25,17 +45,18 @@ def _arch():
 
 def _load():
     try:
-        with open(_CACHE) as f:
+        with open(cache_path()) as f:
             return json.load(f)
     except (OSError, ValueError):
         return {}
 
 
 def _store(d):
-    tmp = _CACHE + ".tmp%d" % os.getpid()
+    path = cache_path()
+    tmp = path + ".tmp%d" % os.getpid()
     with open(tmp, "w") as f:
         json.dump(d, f, indent=1, sort_keys=True)
-    os.replace(tmp, _CACHE)
+    os.replace(tmp, path)
 
 
 def _time(fn, reps=5):
@@ -50,37 +71,105 @@ def _time(fn, reps=5):
     return a.elapsed_time(b) / reps
 
 
-def persistent_grid(plan, candidates=None, data=None):
-    """Best workgroup count for `plan` (cached).  `data`: optional list of the
-    plan's device tensors, used for the parity gate (restored between runs)."""
-    info = plan.info()
-    key = "%s/%s/units%d/tiles%d" % (_arch(), source_digest(), info["units"], info["tiles"])
-    cache = _load()
-    if key in cache:
-        return int(cache[key])
-    cus = torch.cuda.get_device_properties(0).multi_processor_count
-    candidates = candidates or [cus, 2 * cus, 3 * cus, 4 * cus]
-    best, best_ms, ref = None, None, None
-    snapshot = [d.clone() for d in data] if data else None
-    for g in candidates:
-        plan.set_grid(g)
-        if snapshot is not None:
-            for d, s in zip(data, snapshot):
-                d.copy_(s)
-            plan.run()
-            plan.status()
-            out = [d.clone() for d in data]
-            if ref is None:
-                ref = out
-            elif not all(torch.equal(x, y) for x, y in zip(out, ref)):
-                continue                       # parity gate: candidate disagrees, never chosen
-        ms = _time(plan.run)
-        plan.status()
-        if best_ms is None or ms < best_ms:
-            best, best_ms = g, ms
-    if snapshot is not None:
+def _gated_choice(candidates, apply, run, data, check, restore_every_run):
+    """Shared candidate loop.  apply(c) selects candidate c; run() computes the
+    outputs in `data` (in place) from the snapshot; returns (best, table)."""
+    snapshot = [d.clone() for d in data]
+
+    def restore():
         for d, s in zip(data, snapshot):
             d.copy_(s)
-    cache[key] = best
+
+    best, best_ms, ref, table = None, None, None, {}
+    for i, c in enumerate(candidates):
+        apply(c)
+        restore()
+        run()
+        torch.cuda.synchronize()
+        out = [d.clone() for d in data]
+        if i == 0:
+            if check is not None and not check(out):
+                restore()
+                raise ParityError("the default candidate %r fails the parity check" % (c,))
+            ref = out
+        elif not all(torch.equal(x, y) for x, y in zip(out, ref)):
+            table[str(c)] = "differs"
+            continue                       # parity gate: a candidate that disagrees is never chosen
+        if restore_every_run:
+            def timed():
+                restore()
+                run()
+            ms = _time(timed)
+        else:
+            ms = _time(run)
+        table[str(c)] = round(ms, 4)
+        if best_ms is None or ms < best_ms:
+            best, best_ms = c, ms
+    restore()
+    return best, table
+
+
+def persistent_grid(plan, data, candidates=None, check=None, force=False):
+    """Best workgroup count for `plan` (cached).  data: the plan's device
+    tensors (restored to their contents on return); check(outputs) -> bool:
+    optional verification of the default candidate's outputs."""
+    info = plan.info()
+    key = "grid/%s/%s/units%d/tiles%d" % (_arch(), source_digest(), info["units"], info["tiles"])
+    cache = _load()
+    if key in cache and not force:
+        return int(cache[key]["choice"])
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    candidates = candidates or [2 * cus, cus, 3 * cus, 4 * cus]
+
+    def run():
+        plan.run()
+        plan.status()                      # a tile that gave up waiting fails the candidate loudly
+
+    best, table = _gated_choice(candidates, plan.set_grid, run, data, check, restore_every_run=False)
+    plan.set_grid(best)
+    cache = _load()
+    cache[key] = {"choice": best, "ms": table}
     _store(cache)
     return best
+
+
+def kernel_config(op, tables, run, data, batch_units, check=None, force=False):
+    """Best compiled kernel instance for `op` ("fwd", "inv", "polymul",
+    "tensor") at the tables' N and a (batch x limbs) shape class, among the
+    instances the library was built with (cached).  run() performs the op on
+    `data` in place; it is timed after every candidate's outputs equal the
+    default's.  Selects the choice in the library and returns its description."""
+    import paper_2109_14704_amd as H
+    cls = H.shape_class(batch_units)
+    key = "kernel/%s/%s/%s/logn%d/%s" % (_arch(), source_digest(), op, tables.log_n, cls)
+    n = H.tune_count(op, tables.log_n)
+    cache = _load()
+    if key in cache and not force:
+        idx = int(cache[key]["choice"])
+        H.tune_select(op, tables.log_n, cls, idx)
+        return H.tune_describe(op, tables.log_n, idx)
+    cands = list(range(n))
+
+    def apply(i):
+        H.tune_select(op, tables.log_n, cls, i)
+
+    best, table = _gated_choice(cands, apply, run, data, check, restore_every_run=True)
+    H.tune_select(op, tables.log_n, cls, best)
+    cache = _load()
+    cache[key] = {"choice": best, "describe": H.tune_describe(op, tables.log_n, best),
+                  "ms": {H.tune_describe(op, tables.log_n, int(k)): v for k, v in table.items()}}
+    _store(cache)
+    return H.tune_describe(op, tables.log_n, best)
+
+
+def apply_cached(op, log_n, batch_units):
+    """Select the cached choice for (op, N, shape class) if there is one;
+    returns its description or None (the library default stays)."""
+    import paper_2109_14704_amd as H
+    cls = H.shape_class(batch_units)
+    key = "kernel/%s/%s/%s/logn%d/%s" % (_arch(), source_digest(), op, log_n, cls)
+    ent = _load().get(key)
+    if not ent:
+        return None
+    H.tune_select(op, log_n, cls, int(ent["choice"]))
+    return H.tune_describe(op, log_n, int(ent["choice"]))

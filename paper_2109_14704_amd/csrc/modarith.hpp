@@ -7,6 +7,8 @@
 // for this ISA).  Moduli satisfy q < 2^60 (so 16q < 2^64).
 #pragma once
 #include <stdint.h>
+
+#include "records.hpp"
 #ifdef HENTT_HOST_TEST
 // Host build of this header for the CPU property tests of the arithmetic.
 #define __device__
@@ -65,11 +67,6 @@ __device__ __forceinline__ uint64_t csubn(uint64_t x, uint64_t nm) {
   return d < x ? d : x;
 }
 __device__ __forceinline__ uint64_t csub(uint64_t x, uint64_t m) { return x >= m ? x - m : x; }
-
-// Moduli constants used by the butterflies.
-struct ModQ {
-  uint64_t q, nq, q2, nq2, q4, nq4;  // q, 2q, 4q and their negations mod 2^64
-};
 
 // Forward (Cooley-Tukey) lazy butterfly, Algorithm 1 with a wider lazy range:
 // X, Y in [0, 8q) on entry and exit (q < 2^60); X' = X + W Y, Y' = X - W Y

@@ -21,25 +21,6 @@
 
 namespace hentt {
 
-struct LimbConst {
-  ModQ m;                   // q, 2q, 4q and their negations mod 2^64
-  uint64_t ninv, ninv_s;    // N^-1 mod q and its Shoup quotient
-  uint64_t ninvw, ninvw_s;  // N^-1 * psi^-brv(1) mod q and its Shoup quotient
-  uint64_t mu;              // floor(2^(2k) / q), k = bit length of q (Barrett)
-  uint32_t k, pad;
-};
-
-static_assert(sizeof(LimbConst) == 96, "limb records are 12 words (documented in the C ABI)");
-
-// Montgomery constants of a limb (R = 2^64).
-struct MontLimb {
-  uint64_t qinv;   // -q^-1 mod 2^64
-  uint64_t r, rs;  // R mod q and its Shoup quotient
-  uint64_t pad;
-};
-
-struct alignas(16) Tw { uint64_t w, ws; };
-
 // LDS padding: one spare element after every 16, so that the lane-strided
 // accesses of every round hit distinct banks.
 __device__ __forceinline__ constexpr uint32_t lds_pad(uint32_t i) { return i + (i >> 4); }
@@ -482,42 +463,6 @@ __global__ __launch_bounds__(1 << (B - E)) void k_inv_blocks(uint64_t *__restric
   load_global_m0<B, E>(v, p, lds, tid);
   inv_block_rounds<B, E, 0, E>(v, LOGN, lds, tid, blockStart, it, c);
   store_global<B, E, L::LO, L::R>(v, p, RoundMap<B, E, L::LO, L::R>::lane_part(tid));
-}
-
-// ------------------------------------------------- design-ladder kernels --
-// Reference points for the kernel-design ladder of section III-B, not used by
-// the hot path.  k_naive_stage is the paper's naive radix-2 baseline: one
-// butterfly per lane and one launch per stage, every stage a round trip of
-// the whole batch through global memory (same butterfly arithmetic as the
-// other kernels).  Stage s pairs j with j + N/2^(s+1) and uses
-// psi_rev[2^s + j / (N/2^s)].  k_reduce8q is its separate last-round
-// reduction from [0, 8q) to [0, q).
-__global__ __launch_bounds__(256) void k_naive_stage(uint64_t *__restrict__ x, const Tw *__restrict__ tw,
-                                                     const LimbConst *__restrict__ lc, uint32_t units,
-                                                     uint32_t limbs, uint32_t logn, uint32_t s) {
-  const uint64_t gid = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-  const uint32_t lh = logn - 1;
-  const uint64_t unit = gid >> lh;  // (batch entry, limb) polynomial
-  if (unit >= units) return;
-  const uint32_t i = (uint32_t)gid & ((1u << lh) - 1);
-  const uint32_t limb = (uint32_t)(unit % limbs);
-  const ModQ m = lc[limb].m;
-  const uint32_t lt = lh - s;  // log2 of the gap
-  const uint32_t grp = i >> lt;
-  const uint32_t j = (grp << (lt + 1)) | (i & ((1u << lt) - 1));
-  uint64_t *p = x + (unit << logn);
-  const Tw w = tw[((size_t)limb << (logn + 1)) + (1u << s) + grp];
-  uint64_t X = p[j], Y = p[j + (1u << lt)];
-  ct_bfly(X, Y, w.w, w.ws, m);
-  p[j] = X;
-  p[j + (1u << lt)] = Y;
-}
-
-__global__ __launch_bounds__(256) void k_reduce8q(uint64_t *__restrict__ x, const LimbConst *__restrict__ lc,
-                                                  uint64_t words, uint32_t limbs, uint32_t logn) {
-  const uint64_t gid = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-  if (gid >= words) return;
-  x[gid] = reduce_8q(x[gid], lc[(uint32_t)((gid >> logn) % limbs)].m);
 }
 
 // ------------------------------------------------------ fused products ----

@@ -69,7 +69,20 @@ def test_status_codes():
     assert L.hentt_ct_tensor(None, None, None, None, 1, 0, None) == -1
     assert L.hentt_ntt_batch(None, 0, 1, None) == -1
     assert L.hentt_tables_destroy(None) == -1
+    assert L.hentt_check_canonical(None, None, 1, None, None, None) == -1
+    assert L.hentt_ntt_batch_status(None, 0, 1) == -1
+    assert L.hentt_batch_plan_set_grid(None, 1) == -1
+    assert L.hentt_batch_plan_destroy(None) == -1
+    assert L.hentt_graph_launch(None, None) == -1
+    assert L.hentt_pool_bytes(None) == -1
+    n = ctypes.c_uint64(1)
+    assert L.hentt_pool_bytes(ctypes.byref(n)) == 0 and n.value == 0     # nothing allocated on the CPU
+    assert L.hentt_rescale(None, None, None, 1, 0, None) == -1
+    assert L.hentt_relin(None, None, None, None, 1, None) == -1
+    assert L.hentt_ct_matmul(None, None, None, None, 1, 1, 1, None) == -1
     assert L.hentt_status_str(-2).decode().startswith("bad modulus")
+    assert "graphs" in L.hentt_status_str(-6).decode()
+    assert "[0, q)" in L.hentt_status_str(-7).decode()
     with pytest.raises(H.HenttError):
         H.psi(good + 2, 12)
 

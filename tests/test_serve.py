@@ -24,6 +24,8 @@ class FakeBackend:
         self.clock, self.delay, self.fail_on = clock, delay, set(fail_on)
         self.launches = 0
         self.groups = []
+        self.inflight = 0          # steps launched and not yet released
+        self.max_inflight = 0
 
     def launch(self, batch, slot=0):
         k = self.launches
@@ -31,6 +33,8 @@ class FakeBackend:
         if k in self.fail_on:
             raise RuntimeError("injected failure on launch %d" % k)
         self.groups.append([(key, [r.rid for r in rs]) for key, rs in batch])
+        self.inflight += 1
+        self.max_inflight = max(self.max_inflight, self.inflight)
         return {"t": self.clock() + self.delay, "batch": batch}
 
     def poll(self, h):
@@ -41,7 +45,7 @@ class FakeBackend:
             r.result = int(np.sum(r.c)) * 31 + int(np.sum(r.d))
 
     def release(self, h):
-        pass
+        self.inflight -= 1
 
 
 def make_req(i, arrival, log_n=14, level=4):
@@ -87,8 +91,9 @@ def test_continuous_batching_admits_arrivals_between_steps():
     for step in be.groups:
         for (ln, lvl), rids in step:
             assert all((reqs[i].log_n, reqs[i].level) == (ln, lvl) for i in rids)
-    # at most `streams` steps in flight at once
-    assert max(len(g) for g in be.groups) >= 1
+    # at most `streams` steps in flight at once, and the limit was reached:
+    # arrivals every 0.5 s against 2 s steps keep two steps in flight
+    assert be.max_inflight == 2 and be.inflight == 0
 
 
 def test_oversized_request_is_rejected_not_blocking():
