@@ -1,14 +1,25 @@
 """Benchmark of the batched negacyclic NTT path on one MI355X.
 
-Default workload (CKKS-level batch): N = 2^15, 16 RNS primes of 50-60 bits,
-64 ciphertexts x 2 polynomials = 128 polynomials per operand; one step is the
-whole path -- forward NTT of A and B, dyadic product, inverse NTT -- run as
-the library's fused polymul.  Inputs are resident in HBM before timing.
+Default run: the three batched workloads, each step timed with inputs
+resident in HBM.
+  * headline -- the uneven batch: 512 polynomials with N from 2^12 to 2^17
+    and 1 to 32 limbs (about 3.6e8 coefficients), forward then inverse, each
+    one persistent launch replayed from a hipGraph at the autotuned grid;
+    the largest single-GPU configuration;
+  * ct_tensor -- 32 ciphertext pairs, N = 2^16, 24 limbs: fused forward
+    transforms, the Mul tensor and the inverse transforms;
+  * ckks_level -- 128 polynomials per operand, N = 2^15, 16 limbs: fused
+    forward transforms, dyadic product, inverse transform.
 
-Prints ONE JSON line: Gcoeff/s (B*L*N coefficients per transform, three
-transforms per step), the roofline of the dominant kernel (HIP-event timed on
-the launching stream), the per-polynomial-launch comparator, and the CPU
-oracle timed on a bounded sample of the same workload.
+Prints ONE JSON line.  `value` is the headline's Gcoeff/s (B L N coefficients
+per transform).  For each workload: the roofline of its dominant kernel
+(HIP events on the launching stream) in compulsory HBM bytes and 32-bit
+multiplies against MI355X's peaks and against the measured stream and
+multiply rates, the VALU-issue figure beside it, the step-level
+T_bound / T_measured, per-kernel times, and the per-polynomial-launch
+comparator.  The CPU oracle is timed on a bounded sample of the headline.
+Other workloads (--workload): ckks_level, ct_tensor, uneven, plain4096,
+rescale, ladder, matmul, routines, serving, micro.
 """
 import argparse
 import json
@@ -29,14 +40,15 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=20,
-                    help="untimed steps; the clocks settle after about 20 steps of the default workload")
-    ap.add_argument("--workload", default="ckks_level",
-                    choices=["ckks_level", "ct_tensor", "plain4096", "uneven", "serving", "ladder", "rescale",
-                             "matmul", "routines"])
+                    help="untimed steps; the clocks settle after about 20 steps of a batched workload")
+    ap.add_argument("--workload", default="headline",
+                    choices=["headline", "ckks_level", "ct_tensor", "plain4096", "uneven", "serving", "ladder",
+                             "rescale", "matmul", "routines", "micro"])
     ap.add_argument("--requests", type=int, default=2200, help="serving: requests per trace (first 200 warm up)")
     ap.add_argument("--grid", type=int, default=0, help="persistent workgroups for the uneven batch (0 = tuned/default)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-per-poly", action="store_true", help="skip the per-polynomial comparator")
+    ap.add_argument("--no-micro", action="store_true", help="skip the stream/multiply microbenchmarks")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU work for the oracle sample")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
@@ -47,16 +59,40 @@ def to_dev(a, torch):
     return torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).to("cuda:0")
 
 
-def _tuned_grid(plan, grid_arg, data=None):
+def _tuned_grid(plan, grid_arg, data):
     if grid_arg:
         return grid_arg
     from paper_2109_14704_amd import autotune
-    return autotune.persistent_grid(plan, data=data)
+    return autotune.persistent_grid(plan, data)
+
+
+def _work_products(info, n_in, n_out, prod_muls, prod_valu):
+    """Per-kernel algorithmic work of a fused product step (polymul or tensor)."""
+    import paper_2109_14704_amd as H
+    from paper_2109_14704_amd import roofline as R
+    n, L = info["N"], info["limbs"]
+    logn = n.bit_length() - 1
+    pec = H.stage_split(logn)[1]
+    tw = lambda polys, st: R.transform_work(n, polys * L, st)
+
+    def kernel(name):
+        base = name.split("<")[0]
+        if base == "k_cols_fwd":
+            return R.Work(16.0 * n_in * L * n) + tw(n_in, pec)
+        if base == "k_cols_inv":
+            return R.Work(16.0 * n_out * L * n) + tw(n_out, pec)
+        if base.startswith("k_prod"):
+            return R.Work(8.0 * (n_in + n_out) * L * n, prod_muls, prod_valu) + tw(n_in + n_out, logn - pec)
+        return None
+
+    step = R.Work(8.0 * (n_in + n_out) * L * n, prod_muls, prod_valu) + tw(n_in + n_out, logn)
+    return kernel, step
 
 
 def setup(name, torch, H, grid_arg=0):
-    """Device-resident operands and the step function for a workload."""
+    """Device-resident operands, the step function and the work accounting of a workload."""
     import workloads
+    from paper_2109_14704_amd import roofline as R
     if name == "ckks_level":
         w = workloads.ckks_level()
         t = H.Tables(w["log_n"], w["moduli"])
@@ -73,8 +109,10 @@ def setup(name, torch, H, grid_arg=0):
 
         info = {"workload": "ckks_level", "N": n, "limbs": L, "polys_per_operand": polys,
                 "ops": "fwd(A), fwd(B), dyadic, inv (fused polymul)"}
-        return dict(step=step, per_poly=per_poly_step, coeffs=3 * polys * L * n, t=t, info=info, w=w,
-                    cpu=lambda k: cpu_ckks(w, k), cpu1=lambda k: cpu_ckks_1core(w, k))
+        kw, sw = _work_products(info, 2 * polys, polys, R.MUL_PROD * polys * L * n, R.VALU_PROD * polys * L * n)
+        return dict(step=step, per_poly=per_poly_step, coeffs=3 * polys * L * n, info=info, kernel_work=kw,
+                    step_work=sw, cpu=lambda k: cpu_ckks(w, k), cpu1=lambda k: cpu_ckks(w, k, threads=1),
+                    sample_limit=polys, keep=(t, A, B, out))
     if name == "ct_tensor":
         w = workloads.ct_tensor()
         t = H.Tables(w["log_n"], w["moduli"])
@@ -91,16 +129,19 @@ def setup(name, torch, H, grid_arg=0):
 
         info = {"workload": "ct_tensor", "N": n, "limbs": L, "ct_pairs": pairs,
                 "ops": "fwd of c0,c1,d0,d1; tensor (c0d0, c0d1+c1d0, c1d1); inv of 3 outputs"}
-        return dict(step=step, per_poly=per_poly_step, coeffs=7 * pairs * L * n, t=t, info=info, w=w,
-                    cpu=lambda k: cpu_tensor(w, k), ctmul=pairs)
+        kw, sw = _work_products(info, 4 * pairs, 3 * pairs, R.MUL_TENSOR * pairs * L * n,
+                                R.VALU_TENSOR * pairs * L * n)
+        return dict(step=step, per_poly=per_poly_step, coeffs=7 * pairs * L * n, info=info, kernel_work=kw,
+                    step_work=sw, cpu=lambda k: cpu_tensor(w, k), sample_limit=pairs, ctmul=pairs,
+                    keep=(t, C, D, out))
     if name == "uneven":
         mods = workloads.moduli("uneven")
         jobs = workloads.uneven_jobs()
         tables = {ln: H.Tables(ln, mods) for ln in sorted(set(ln for ln, _ in jobs))}
         xs = [to_dev(workloads.uneven_operand(j, ln, L, mods), torch) for j, (ln, L) in enumerate(jobs)]
-        plan_f = H.BatchPlan([(x, tables[ln], L) for x, (ln, L) in zip(xs, jobs)], +1)
-        plan_i = H.BatchPlan([(x, tables[ln], L) for x, (ln, L) in zip(xs, jobs)], -1)
-        grid = _tuned_grid(plan_f, grid_arg, data=xs)
+        spec = [(x, tables[ln], L) for x, (ln, L) in zip(xs, jobs)]
+        plan_f, plan_i = H.BatchPlan(spec, +1), H.BatchPlan(spec, -1)
+        grid = _tuned_grid(plan_f, grid_arg, xs)
         plan_f.set_grid(grid)
         plan_i.set_grid(grid)
         plan_f.capture()
@@ -111,6 +152,10 @@ def setup(name, torch, H, grid_arg=0):
             plan_f.replay()
             plan_i.replay()
 
+        def check():              # a tile that gave up waiting would make the step look faster
+            plan_f.status()
+            plan_i.status()
+
         views = {(ln, L): tables[ln].view(L) for ln, L in set(jobs)}
 
         def per_poly_step():              # one launch sequence per polynomial
@@ -119,15 +164,24 @@ def setup(name, torch, H, grid_arg=0):
             for x, (ln, L) in zip(xs, jobs):
                 H.ntt_inv(views[(ln, L)], x)
 
-        info = {"workload": "uneven", "jobs": len(jobs), "N_range": [1 << 12, 1 << 17], "limbs_range": [1, 32],
-                "coefficients": coeffs, "ops": "fwd then inv, each one persistent launch, hipGraph replay",
-                "persistent_grid": grid}
         def prof_step():                 # same launches outside the graph, so each is event-timed
             plan_f.run()
             plan_i.run()
 
-        return dict(step=step, per_poly=per_poly_step, coeffs=2 * coeffs, t=tables, info=info, w={"x": xs},
-                    cpu=lambda k: cpu_uneven(jobs, mods, k), plans=(plan_f, plan_i), prof_step=prof_step)
+        direction = R.Work(16.0 * coeffs)
+        for ln, L in jobs:
+            direction = direction + R.transform_work(1 << ln, L)
+
+        def kw(name):
+            return direction if name.split("<")[0] in ("k_batch_fwd", "k_batch_inv") else None
+
+        info = {"workload": "uneven", "jobs": len(jobs), "N_range": [1 << 12, 1 << 17], "limbs_range": [1, 32],
+                "coefficients": coeffs, "ops": "fwd then inv, each one persistent launch, hipGraph replay",
+                "persistent_grid": grid}
+        return dict(step=step, per_poly=per_poly_step, coeffs=2 * coeffs, info=info, kernel_work=kw,
+                    step_work=direction + direction, cpu=lambda k: cpu_uneven(jobs, mods, k),
+                    cpu1=lambda k: cpu_uneven(jobs, mods, k, threads=1), sample_limit=len(jobs), check=check,
+                    prof_step=prof_step, keep=(tables, xs, views, plan_f, plan_i))
     if name == "rescale":
         # RS after Mul at the top of the ct_tensor chain: 32 ciphertexts (64
         # polynomials) of N = 2^16 at 24 limbs, NTT domain -> 23 limbs
@@ -153,10 +207,28 @@ def setup(name, torch, H, grid_arg=0):
             H.rescale(t, tmp, out=out)
             H.ntt_fwd(lower, out)
 
+        tc = H.stage_split(logn)[0]
+        units = polys * (L - 1)
+
+        def kw(name):
+            # column pass: reads the last limb's words once per polynomial and
+            # writes one scratch word per output coefficient; the block pass
+            # reads it and c_i and writes the result, with the epilogue
+            base = name.split("<")[0]
+            if base == "k_rs_cols":
+                return R.Work(8.0 * (units + polys) * n, R.MUL_RS_PRO * units * n) + R.transform_work(n, units, tc)
+            if base == "k_rs_blocks":
+                return (R.Work(24.0 * units * n, R.MUL_SHOUP * units * n, R.VALU_RS_EPI * units * n)
+                        + R.transform_work(n, units, logn - tc))
+            return None
+
+        step_work = (R.Work(8.0 * (polys * L + units) * n, (R.MUL_RS_PRO + R.MUL_SHOUP) * units * n)
+                     + R.transform_work(n, units + polys))
         info = {"workload": "rescale", "N": n, "limbs": L, "polys": polys,
                 "ops": "RS in the NTT domain: inverse of the last limb, fused forward + subtract + scale per limb"}
-        return dict(step=step, per_poly=unfused_step, coeffs=polys * (L - 1) * n, t=t, info=info,
-                    w={"x": [None] * polys}, cpu=lambda k: cpu_rescale(mods, logn, k))
+        return dict(step=step, per_poly=unfused_step, coeffs=polys * (L - 1) * n, info=info, kernel_work=kw,
+                    step_work=step_work, cpu=lambda k: cpu_rescale(mods, logn, k), sample_limit=polys,
+                    keep=(t, C, out, tmp, lower))
     w = workloads.plain4096()
     t = H.Tables(12, w["moduli"])
     X = to_dev(w["x"], torch)
@@ -170,29 +242,20 @@ def setup(name, torch, H, grid_arg=0):
             H.ntt_fwd(t, X[i:i + 1])
             H.ntt_inv(t, X[i:i + 1])
 
+    one = R.Work(16.0 * 8 * 4096) + R.transform_work(4096, 8)
     info = {"workload": "plain4096", "N": 4096, "limbs": 1, "polys": 8, "ops": "fwd, inv"}
-    return dict(step=step, per_poly=per_poly_step, coeffs=2 * 8 * 4096, t=t, info=info, w=w,
-                cpu=lambda k: cpu_plain(w, k))
+    return dict(step=step, per_poly=per_poly_step, coeffs=2 * 8 * 4096, info=info,
+                kernel_work=lambda name: one if name.split("<")[0] in ("k_fwd_whole", "k_inv_whole") else None,
+                step_work=one + one, cpu=lambda k: cpu_plain(w, k), sample_limit=10 ** 6, keep=(t, X))
 
 
 # ---------------------------------------------------------------- CPU oracle
-def cpu_ckks(w, k):
+def cpu_ckks(w, k, threads=0):
     import oracle
     a, b = w["a"][:k], w["b"][:k]
     t0 = time.perf_counter()
-    oracle.batch_polymul(a, b, w["moduli"])
-    dt = time.perf_counter() - t0
-    return dt, 3 * a.size
-
-
-def cpu_ckks_1core(w, k):
-    """The CKKS-level oracle on one host thread."""
-    import oracle
-    a, b = w["a"][:k], w["b"][:k]
-    t0 = time.perf_counter()
-    oracle.batch_polymul(a, b, w["moduli"], threads=1)
-    dt = time.perf_counter() - t0
-    return dt, 3 * a.size
+    oracle.batch_polymul(a, b, w["moduli"], threads=threads)
+    return time.perf_counter() - t0, 3 * a.size
 
 
 def cpu_tensor(w, k):
@@ -200,19 +263,19 @@ def cpu_tensor(w, k):
     c, d = w["c"][:k], w["d"][:k]
     t0 = time.perf_counter()
     oracle.batch_ct_tensor_coeff(c, d, w["moduli"])
-    dt = time.perf_counter() - t0
-    return dt, 7 * c[:, 0].size
+    return time.perf_counter() - t0, 7 * c[:, 0].size
 
 
-def cpu_uneven(jobs, mods, k):
+def cpu_uneven(jobs, mods, k, threads=0):
+    """The oracle's forward then inverse transform of the first k jobs."""
     import oracle
     import workloads
+    xs = [workloads.uneven_operand(j, ln, L, mods) for j, (ln, L) in enumerate(jobs[:k])]
     t0 = time.perf_counter()
     coeffs = 0
-    for j, (ln, L) in enumerate(jobs[:k]):
-        x = workloads.uneven_operand(j, ln, L, mods)
-        X = oracle.batch_ntt(x, mods[:L], +1)
-        oracle.batch_ntt(X, mods[:L], -1)
+    for x, (ln, L) in zip(xs, jobs[:k]):
+        X = oracle.batch_ntt(x, mods[:L], +1, threads=threads)
+        oracle.batch_ntt(X, mods[:L], -1, threads=threads)
         coeffs += 2 * x.size
     return time.perf_counter() - t0, coeffs
 
@@ -233,15 +296,14 @@ def cpu_plain(w, k):
     for _ in range(k):
         X = oracle.batch_ntt(x, w["moduli"], +1)
         oracle.batch_ntt(X, w["moduli"], -1)
-    dt = time.perf_counter() - t0
-    return dt, 2 * x.size * k
+    return time.perf_counter() - t0, 2 * x.size * k
 
 
 def cpu_baseline(s, target_s, one_core=False):
+    """The oracle on the host, on the first k batch entries (jobs) of the
+    workload, k grown until the sample takes about target_s."""
     import oracle
-    k, limit = 1, len(s["w"].get("a", s["w"].get("c", s["w"].get("x"))))
-    if s["info"]["workload"] == "uneven":
-        k = 4
+    k, limit = 1, s["sample_limit"]
     cpu = s["cpu1"] if one_core else s["cpu"]
     dt, coeffs = cpu(k)
     while dt < target_s / 2 and k < limit:      # grow the sample to about the target time
@@ -254,135 +316,146 @@ def cpu_baseline(s, target_s, one_core=False):
         for _ in range(reps):
             d1, c1 = cpu(k)
             dt, coeffs = dt + d1, coeffs + c1
-    return {"value": coeffs / dt / 1e9, "unit": "Gcoeff/s", "cores": 1 if one_core else oracle.max_threads(), "kind": "oracle",
-            "sample": "%d batch entr%s of the same workload%s (radix-2 oracle, %s), %.1f s"
-                      % (k, "y" if k == 1 else "ies", ", %d times" % reps if reps > 1 else "",
+    unit = "jobs" if s["info"]["workload"] == "uneven" else "batch entries"
+    return {"value": coeffs / dt / 1e9, "unit": "Gcoeff/s", "cores": 1 if one_core else oracle.max_threads(),
+            "kind": "oracle",
+            "sample": "the first %d %s of the same workload%s (radix-2 oracle, %s), %.1f s"
+                      % (k, unit, ", %d times" % reps if reps > 1 else "",
                          "one thread" if one_core else "OpenMP over (batch, limb)", dt)}
 
 
-# ---------------------------------------------------------------- roofline
-# Algorithmic ALU work in VALU lane-operations (gfx950 has no 64-bit
-# multiplier; v_mad_u64_u32 / v_mul_hi_u32 / v_mul_lo_u32 issue at full rate, so
-# every VALU op costs one issue slot):
-VALU_BFLY = 21     # Harvey/Shoup butterfly: 9 32-bit multiplies + 12 adds, compares, selects
-VALU_PROD = 19     # Montgomery product a b R^-1 mod q: 128-bit product, low product by -q^-1, high product by q
-VALU_TENSOR = 68   # c0d0, c1d1 (2 x 19) + c0d1 + c1d0 with one Montgomery reduction (30)
-VALU_RS_EPI = 17   # rescale epilogue: Shoup product by qL^-1 (9 + adds) and a reduction from [0, 4q)
-VALU_MAC = 83      # one matMul product term, k >= 3: the tensor's Montgomery products (68), three lazy additions (5 each)
-VALU_MAC_B = 121   # one matMul product term, k <= 2: the tensor's three outputs accumulated with Barrett mad_mod
-VALU_KS_MAC = 24   # key switch, per digit word and key component: Montgomery product (19), lazy addition (5)
-VALU_KS_FIN = 20   # key switch, per output word: Shoup product by R mod q (12), reduction from [0, 4q) (8)
-VALU_KS_FIN_C = 38 # the same plus P c_s: a second Shoup product, an addition, a reduction from [0, 8q)
+# ---------------------------------------------------------------- timing
+def time_steps(step, steps, warmup, torch):
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
 
 
-def kernel_work(name, info):
-    """Algorithmic HBM bytes and VALU operations of ONE launch of `name` in
-    the benchmarked step: per-unit figures times the units one launch handles.
-    Bytes: every coefficient word a launch must read once and write once
-    (8 B each).  ALU: VALU_BFLY per butterfly, N/2 butterflies per stage per
-    polynomial limb, plus the products."""
-    import paper_2109_14704_amd as H
-    n, L = info["N"], info["limbs"]
-    logn = n.bit_length() - 1
-    t_cols, p_cols = H.stage_split(logn)                   # stages in the column passes (library plan)
-    if info["workload"] == "rescale":
-        # column pass: reads the last limb's words once per polynomial (its
-        # other reads, one per output limb, hit the caches) and writes one
-        # scratch word per output coefficient; the block pass reads it and c_i
-        # and writes the result; the epilogue is about one Shoup product and a
-        # reduction
-        units = info["polys"] * (L - 1)
-        base = name.split("<")[0]
-        if base == "k_rs_cols":
-            return 8.0 * (units + info["polys"]) * n, VALU_BFLY * units * (n // 2) * t_cols
-        if base == "k_rs_blocks":
-            return 24.0 * units * n, VALU_BFLY * units * (n // 2) * (logn - t_cols) + VALU_RS_EPI * units * n
-        return None, None
-    if info["workload"] == "ckks_level":
-        p = info["polys_per_operand"]
-        n_in, n_out, prod_mul = 2 * p, p, VALU_PROD * p * L * n
-    elif info["workload"] == "ct_tensor":
-        c = info["ct_pairs"]
-        n_in, n_out, prod_mul = 4 * c, 3 * c, VALU_TENSOR * c * L * n
-    else:
-        n_in = n_out = info["polys"]
-        prod_mul = 0
-    bfly = lambda polys, stages: VALU_BFLY * polys * L * (n // 2) * stages
-    base = name.split("<")[0]
-    ec = p_cols if info["workload"] in ("ckks_level", "ct_tensor") else t_cols
-    if base == "k_cols_fwd":
-        return 16.0 * n_in * L * n, bfly(n_in, ec)
-    if base == "k_cols_inv":
-        return 16.0 * n_out * L * n, bfly(n_out, ec)
-    if base.startswith("k_prod"):
-        stages = logn - ec
-        return 8.0 * (n_in + n_out) * L * n, bfly(n_in + n_out, stages) + prod_mul
-    if base in ("k_fwd_whole", "k_inv_whole"):
-        return 16.0 * n_in * L * n, bfly(n_in, logn)
-    if base in ("k_fwd_blocks", "k_inv_blocks"):
-        return 16.0 * n_in * L * n, bfly(n_in, logn - t_cols)
-    return None, None
-
-
-def batch_work(info, jobs):
-    """One persistent launch over the uneven batch: each (polynomial, limb) of
-    N = 2^12 is read and written once, larger N twice (two passes); butterflies
-    (N/2) log2 N per (polynomial, limb)."""
-    nbytes = sum(L * (1 << ln) * (16 if ln == 12 else 32) for ln, L in jobs)
-    muls = sum(VALU_BFLY * L * (1 << (ln - 1)) * ln for ln, L in jobs)
-    return float(nbytes), float(muls)
-
-
-def ks_work(batch, l, logn, ec):
-    """ONE launch of the key-switch block kernel (k_ks_blocks): per (batch
-    entry, target prime t <= l, digit j < l) the last logn - ec forward stages
-    of a digit and two Montgomery multiply-adds per word; per output word the
-    finishing products.  Bytes: the column-pass words read once, the key read
-    once (shared by the batch), c0 and c1 read once, the accumulators written."""
-    n = 1 << logn
-    L1 = l + 1
-    ops = batch * L1 * l * (VALU_BFLY * (n // 2) * (logn - ec) + 2 * VALU_KS_MAC * n)
-    ops += batch * 2 * n * (l * VALU_KS_FIN_C + VALU_KS_FIN)
-    nbytes = 8.0 * n * (batch * l * L1 + l * 2 * L1 + batch * 2 * l + batch * 2 * L1)
-    return nbytes, float(ops)
-
-
-def alu_or_hbm(nbytes, ops, per_launch_s):
-    """Roofline object of one launch against the binding roof."""
+def measure(s, args, measured, torch, H):
+    """Times one workload: step, per-kernel launches, roofline, comparator."""
     from paper_2109_14704_amd import roofline as R
-    if nbytes / (R.HBM_PEAK_GBS * 1e9) >= ops / (R.VALU_PEAK_TOPS * 1e12):
-        ach = nbytes / per_launch_s / 1e9
-        return {"bound": "hbm", "achieved": round(ach, 1), "peak": R.HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / R.HBM_PEAK_GBS, 4)}
-    ach = ops / per_launch_s / 1e12
-    return {"bound": "alu", "achieved": round(ach, 3), "peak": round(R.VALU_PEAK_TOPS, 2), "unit": "T VALU-op/s",
-            "frac": round(ach / R.VALU_PEAK_TOPS, 4)}
-
-
-def roofline(prof, info, steps):
-    from paper_2109_14704_amd import roofline as R
-    # dominant kernel by total time
-    name, (ms, cnt) = max(prof.items(), key=lambda kv: kv[1][0])
-    per_launch_s = ms / 1e3 / cnt
-    if name.startswith("k_batch"):
-        import workloads
-        nbytes, muls = batch_work(info, workloads.uneven_jobs())
-    else:
-        nbytes, muls = kernel_work(name, info)
-    if nbytes is None:
-        return None, name, per_launch_s
-    t_hbm = nbytes / (R.HBM_PEAK_GBS * 1e9)
-    t_alu = muls / (R.VALU_PEAK_TOPS * 1e12)
-    if t_hbm >= t_alu:
-        ach = nbytes / per_launch_s / 1e9
-        rl = {"bound": "hbm", "achieved": round(ach, 1), "peak": R.HBM_PEAK_GBS, "unit": "GB/s",
-              "frac": round(ach / R.HBM_PEAK_GBS, 4)}
-    else:
-        ach = muls / per_launch_s / 1e12
-        rl = {"bound": "alu", "achieved": round(ach, 3), "peak": round(R.VALU_PEAK_TOPS, 2),
-              "unit": "T VALU-op/s", "frac": round(ach / R.VALU_PEAK_TOPS, 4)}
+    ms = time_steps(s["step"], args.steps, args.warmup, torch)
+    if "check" in s:
+        s["check"]()
+    value = s["coeffs"] / (ms / 1e3) / 1e9
+    print("bench: %s %.3f ms/step (%.1f Gcoeff/s)" % (s["info"]["workload"], ms, value), file=sys.stderr, flush=True)
+    # per-kernel durations: HIP events on the launching stream, a separate pass
+    H.prof_enable(True)
+    prof_steps = max(3, min(args.steps, 10))
+    for _ in range(prof_steps):
+        s.get("prof_step", s["step"])()
+    torch.cuda.synchronize()
+    prof = H.prof_read()
+    H.prof_enable(False)
+    name, (kms, cnt) = max(prof.items(), key=lambda kv: kv[1][0])
+    per_launch_s = kms / 1e3 / cnt
+    w = s["kernel_work"](name)
+    rl = R.roof(w, per_launch_s, measured) if w is not None else {}
     rl.update({"kernel": name, "launch_ms": round(per_launch_s * 1e3, 4), "traffic": R.stored_traffic(name)})
-    return rl, name, per_launch_s
+    out = {"value": round(value, 3), "unit": "Gcoeff/s", "ms_per_step": round(ms, 4), "config": s["info"],
+           "roofline": rl, "kernels_ms": {k: round(v[0] / v[1], 4) for k, v in sorted(prof.items())}}
+    if measured:
+        out["step_roofline"] = R.step_roof(s["step_work"], ms / 1e3, measured)
+    if "ctmul" in s:
+        out["ct_mul_per_s"] = round(s["ctmul"] / (ms / 1e3), 1)
+    if not args.no_per_poly:
+        s["per_poly"]()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 3
+        a.record()
+        for _ in range(reps):
+            s["per_poly"]()
+        b.record()
+        torch.cuda.synchronize()
+        pms = a.elapsed_time(b) / reps
+        if s["info"]["workload"] == "rescale":      # the comparator is the unfused sequence
+            out["unfused"] = {"ms_per_step": round(pms, 4), "value": round(s["coeffs"] / (pms / 1e3) / 1e9, 3),
+                              "unit": "Gcoeff/s", "fused_speedup": round(pms / ms, 3),
+                              "ops": "inverse of every limb, coefficient rescale, forward of the rest"}
+        else:
+            out["per_poly"] = {"ms_per_step": round(pms, 4), "value": round(s["coeffs"] / (pms / 1e3) / 1e9, 3),
+                               "unit": "Gcoeff/s", "batched_speedup": round(pms / ms, 3)}
+    return out
+
+
+def micro_rates(args):
+    if args.no_micro:
+        return None
+    from paper_2109_14704_amd import microbench
+    t0 = time.perf_counter()
+    r = microbench.measure_all()
+    print("bench: measured rates %s (%.1f s)" % (json.dumps(r), time.perf_counter() - t0), file=sys.stderr,
+          flush=True)
+    return r
+
+
+def release(s, torch, H):
+    s.clear()
+    import gc
+    gc.collect()
+    torch.cuda.synchronize()
+    H.pool_trim()
+    torch.cuda.empty_cache()
+
+
+def bench_batched(args):
+    import torch
+    import paper_2109_14704_amd as H
+    H.lib()
+    measured = micro_rates(args)
+    names = ["uneven", "ct_tensor", "ckks_level"] if args.workload == "headline" else [args.workload]
+    results, cpu = {}, {}
+    for nm in names:
+        print("bench: setting up workload %s" % nm, file=sys.stderr, flush=True)
+        s = setup(nm, torch, H, args.grid)
+        results[nm] = measure(s, args, measured, torch, H)
+        if nm == names[0] and not args.no_cpu:
+            cpu = {k: s[k] for k in ("cpu", "cpu1", "sample_limit", "info") if k in s}
+        release(s, torch, H)
+    head = results[names[0]]
+    result = {"metric": METRIC, "value": head["value"], "unit": "Gcoeff/s", "n_gpus": 1, "steps": args.steps,
+              "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True,
+              "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic"}
+    result.update({k: v for k, v in head.items() if k not in ("value", "unit", "ms_per_step")})
+    if len(names) > 1:
+        result["workloads"] = {nm: results[nm] for nm in names[1:]}
+    if measured:
+        result["measured_rates"] = measured
+    if args.calib_copy:
+        src = torch.ones(1 << 27, dtype=torch.int64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    if cpu:
+        s = cpu
+        print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
+        result["cpu_baseline"] = cpu_baseline(s, args.cpu_seconds)
+        if "cpu1" in s:                          # the same oracle on one host thread, a shorter sample
+            result["cpu_baseline_1core"] = cpu_baseline(s, args.cpu_seconds / 3, one_core=True)
+    print(json.dumps(result), flush=True)
+
+
+def bench_micro(args):
+    import torch  # noqa: F401
+    r = micro_rates(args)
+    from paper_2109_14704_amd import roofline as R
+    print(json.dumps({"metric": "measured stream bandwidth and multiply issue rates", "value": r["mul_mix_tops"],
+                      "unit": "T int32-mul/s", "n_gpus": 1, "steps": 1, "warmup": 1, "higher_is_better": True,
+                      "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+                      "config": {"workload": "micro"}, "measured_rates": r,
+                      "published_peaks": {"hbm_gbs": R.HBM_PEAK_GBS, "valu_tops": round(R.VALU_PEAK_TOPS, 2)}}),
+          flush=True)
 
 
 def bench_ladder(args):
@@ -404,8 +477,9 @@ def bench_ladder(args):
     for l, q in enumerate(mods):                  # uniform [0, q) per limb, on the device
         x[:, l].copy_(torch.randint(0, q, (polys, n), generator=gen, device="cuda:0", dtype=torch.int64))
     coeffs = polys * L * n
-    ops = 21.0 * polys * L * (n // 2) * logn
     from paper_2109_14704_amd import roofline as R
+    tw = R.transform_work(n, polys * L)
+    one = R.Work(16.0 * coeffs) + tw
     designs = [(H.VARIANT_NAIVE, "naive radix-2, one global-memory launch per stage"),
                (H.VARIANT_STAGED_R2, "4 naive global stages + LDS blocks of 2048, radix-2 rounds"),
                (H.VARIANT_STAGED_R4, "column pass + LDS blocks of 4096, radix-4 rounds"),
@@ -425,8 +499,9 @@ def bench_ladder(args):
         b.record()
         torch.cuda.synchronize()
         ms = a.elapsed_time(b) / k
+        rl = R.roof(one, ms / 1e3)
         rows.append({"variant": v, "design": desc, "ms": round(ms, 4), "gcoeff_s": round(coeffs / ms / 1e6, 3),
-                     "alu_frac": round(ops / (ms / 1e3) / (R.VALU_PEAK_TOPS * 1e12), 4)})
+                     "frac": rl["frac"], "bound": rl["bound"], "valu_frac": rl["valu"]["frac"]})
     base = rows[0]["ms"]
     for r in rows:
         r["x_naive"] = round(base / r["ms"], 2)
@@ -438,7 +513,12 @@ def bench_ladder(args):
     prof = H.prof_read()
     H.prof_enable(False)
     info = {"workload": "ladder", "N": n, "limbs": L, "polys": polys, "ops": "fwd (the paper's NTT shape)"}
-    rl, _, _ = roofline(prof, info, 3)
+    name, (kms, cnt) = max(prof.items(), key=lambda kv: kv[1][0])
+    tc = H.stage_split(logn)[0]
+    kwork = (R.Work(16.0 * coeffs) + R.transform_work(n, polys * L, logn - tc)) if name.startswith("k_fwd_blocks") \
+        else (R.Work(16.0 * coeffs) + R.transform_work(n, polys * L, tc))
+    rl = R.roof(kwork, kms / 1e3 / cnt)
+    rl.update({"kernel": name, "launch_ms": round(kms / cnt, 4), "traffic": R.stored_traffic(name)})
     result = {"metric": METRIC, "value": lib_row["gcoeff_s"], "unit": "Gcoeff/s", "n_gpus": 1,
               "steps": max(3, args.steps // 3), "warmup": max(2, args.warmup // 4), "ms_per_step": lib_row["ms"],
               "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
@@ -452,8 +532,8 @@ def bench_matmul(args):
     IV-E): C += A*B with ciphertext elements of N = 8192 over 4 limbs, NTT
     domain, 100x100x1 and 10x9x8 (m x n x k).  Value: element ciphertext
     products per second on 100x100x1.  Roofline against the compulsory bytes
-    (A and B once, C read and written) and VALU_MAC ops per product term
-    (VALU_MAC_B for k <= 2, which the kernel accumulates with Barrett)."""
+    (A and B once, C read and written) and the tensor's multiplies per
+    product term."""
     import torch
     import workloads
     import paper_2109_14704_amd as H
@@ -485,15 +565,10 @@ def bench_matmul(args):
         b.record()
         torch.cuda.synchronize()
         ms = a.elapsed_time(b) / reps
-        nbytes = 8.0 * L * n_ * (2 * m * k + 2 * k * n + 6 * m * n)
-        ops = float(VALU_MAC if k >= 3 else VALU_MAC_B) * m * n * k * L * n_
-        t_hbm, t_alu = nbytes / (R.HBM_PEAK_GBS * 1e9), ops / (R.VALU_PEAK_TOPS * 1e12)
-        if t_hbm >= t_alu:
-            rl = {"bound": "hbm", "achieved": round(nbytes / ms / 1e6, 1), "peak": R.HBM_PEAK_GBS, "unit": "GB/s",
-                  "frac": round(nbytes / ms / 1e6 / R.HBM_PEAK_GBS, 4)}
-        else:
-            rl = {"bound": "alu", "achieved": round(ops / ms / 1e9, 3), "peak": round(R.VALU_PEAK_TOPS, 2),
-                  "unit": "T VALU-op/s", "frac": round(ops / ms / 1e9 / R.VALU_PEAK_TOPS, 4)}
+        terms = m * n * k * L * n_
+        work = R.Work(8.0 * L * n_ * (2 * m * k + 2 * k * n + 6 * m * n), R.MUL_TENSOR * terms,
+                      (R.VALU_MAC if k >= 3 else R.VALU_MAC_B) * terms)
+        rl = R.roof(work, ms / 1e3)
         rl.update({"kernel": "k_ct_matmul<13>", "launch_ms": round(ms, 4), "traffic": R.stored_traffic("k_ct_matmul<13>")})
         rows.append({"shape": "%dx%dx%d" % (m, n, k), "ms": round(ms, 4),
                      "element_products_per_s": round(m * n * k / ms * 1e3, 1), "roofline": rl})
@@ -506,6 +581,22 @@ def bench_matmul(args):
               "ms_per_step": first["ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
               "dtype": "u64", "data": "synthetic", "config": info, "roofline": first["roofline"], "shapes": rows}
     print(json.dumps(result), flush=True)
+
+
+def ks_work(batch, l, logn, ec):
+    """ONE launch of the key-switch block kernel (k_ks_blocks): per (batch
+    entry, target prime t <= l, digit j < l) the last logn - ec forward stages
+    of a digit and its products with both key components; per output word the
+    finishing products.  Bytes: the column-pass words read once, the key read
+    once (shared by the batch), c0 and c1 read once, the accumulators written."""
+    from paper_2109_14704_amd import roofline as R
+    n = 1 << logn
+    L1 = l + 1
+    w = R.transform_work(n, batch * L1 * l, logn - ec)
+    muls = batch * L1 * l * R.MUL_KS_MAC * n + batch * 2 * n * (l * 2 * R.MUL_SHOUP + R.MUL_SHOUP)
+    valu = batch * L1 * l * 2 * R.VALU_KS_MAC * n + batch * 2 * n * (l * R.VALU_KS_FIN_C + R.VALU_KS_FIN)
+    nbytes = 8.0 * n * (batch * l * L1 + l * 2 * L1 + batch * 2 * l + batch * 2 * L1)
+    return w + R.Work(nbytes, muls, valu)
 
 
 def bench_routines(args):
@@ -574,8 +665,7 @@ def bench_routines(args):
     rl = None
     if kname in prof:               # the profiled launches ran at batch 32
         per_launch_s = prof[kname][0] / 1e3 / prof[kname][1]
-        nbytes, ops = ks_work(32, l, logn, 5 if logn >= 15 else logn - 12)   # the key switch's column stages
-        rl = alu_or_hbm(nbytes, ops, per_launch_s)
+        rl = R.roof(ks_work(32, l, logn, 5 if logn >= 15 else logn - 12), per_launch_s)
         rl.update({"kernel": kname, "launch_ms": round(per_launch_s * 1e3, 4), "traffic": R.stored_traffic(kname)})
     result = {"metric": METRIC, "value": value["per_s"], "unit": "MulLinRS/s", "n_gpus": 1,
               "steps": max(5, args.steps), "warmup": max(3, args.warmup // 2), "ms_per_step": value["us"] / 1e3,
@@ -653,99 +743,13 @@ def bench_serving(args):
 
 def main():
     args = parse()
-    if args.workload == "routines":
-        if args.gpus != 1:
-            print("bench.py: one GPU only", file=sys.stderr)
-            sys.exit(2)
-        return bench_routines(args)
-    if args.workload == "matmul":
-        if args.gpus != 1:
-            print("bench.py: one GPU only", file=sys.stderr)
-            sys.exit(2)
-        return bench_matmul(args)
-    if args.workload == "ladder":
-        if args.gpus != 1:
-            print("bench.py: one GPU only", file=sys.stderr)
-            sys.exit(2)
-        return bench_ladder(args)
-    if args.workload == "serving":
-        if args.gpus != 1:
-            print("bench.py: one GPU only", file=sys.stderr)
-            sys.exit(2)
-        return bench_serving(args)
     if args.gpus != 1:
         print("bench.py: this build measures one GPU; --gpus %d is not supported (the path shards by batch "
               "with no exchange, see the design notes)" % args.gpus, file=sys.stderr)
         sys.exit(2)
-    import torch
-    import paper_2109_14704_amd as H
-    H.lib()
-    print("bench: setting up workload %s" % args.workload, file=sys.stderr, flush=True)
-    s = setup(args.workload, torch, H, args.grid)
-    step = s["step"]
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t_wall = time.perf_counter()
-    e0.record()
-    for _ in range(args.steps):
-        step()
-    e1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_wall
-    ms = e0.elapsed_time(e1) / args.steps
-    value = s["coeffs"] / (ms / 1e3) / 1e9
-    print("bench: %.3f ms/step (%.1f Gcoeff/s), wall %.3f s" % (ms, value, wall), file=sys.stderr, flush=True)
-
-    # per-kernel durations (HIP events on the launching stream), separate pass
-    H.prof_enable(True)
-    prof_steps = max(3, min(args.steps, 10))
-    for _ in range(prof_steps):
-        s.get("prof_step", step)()
-    torch.cuda.synchronize()
-    prof = H.prof_read()
-    H.prof_enable(False)
-    rl, kname, kdur = roofline(prof, s["info"], prof_steps)
-
-    result = {"metric": METRIC, "value": round(value, 3), "unit": "Gcoeff/s", "n_gpus": 1, "steps": args.steps,
-              "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
-              "vs_baseline": None, "dtype": "u64", "data": "synthetic", "config": s["info"], "roofline": rl,
-              "kernels_ms": {k: round(v[0] / v[1], 4) for k, v in sorted(prof.items())}}
-    if "ctmul" in s:
-        result["ct_mul_per_s"] = round(s["ctmul"] / (ms / 1e3), 1)
-    if not args.no_per_poly:
-        s["per_poly"]()
-        torch.cuda.synchronize()
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        reps = 3
-        a.record()
-        for _ in range(reps):
-            s["per_poly"]()
-        b.record()
-        torch.cuda.synchronize()
-        pms = a.elapsed_time(b) / reps
-        if s["info"]["workload"] == "rescale":      # the comparator is the unfused sequence
-            result["unfused"] = {"ms_per_step": round(pms, 4), "value": round(s["coeffs"] / (pms / 1e3) / 1e9, 3),
-                                 "unit": "Gcoeff/s", "fused_speedup": round(pms / ms, 3),
-                                 "ops": "inverse of every limb, coefficient rescale, forward of the rest"}
-        else:
-            result["per_poly"] = {"ms_per_step": round(pms, 4), "value": round(s["coeffs"] / (pms / 1e3) / 1e9, 3),
-                                  "unit": "Gcoeff/s", "batched_speedup": round(pms / ms, 3)}
-    if args.calib_copy:
-        src = torch.ones(1 << 27, dtype=torch.int64, device="cuda:0")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-    if not args.no_cpu:
-        print("bench: timing the CPU oracle", file=sys.stderr, flush=True)
-        result["cpu_baseline"] = cpu_baseline(s, args.cpu_seconds)
-        if "cpu1" in s:                          # the same oracle on one host thread, a shorter sample
-            result["cpu_baseline_1core"] = cpu_baseline(s, args.cpu_seconds / 3, one_core=True)
-    print(json.dumps(result), flush=True)
+    fn = {"routines": bench_routines, "matmul": bench_matmul, "ladder": bench_ladder, "serving": bench_serving,
+          "micro": bench_micro}.get(args.workload, bench_batched)
+    fn(args)
 
 
 if __name__ == "__main__":
