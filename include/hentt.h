@@ -47,6 +47,7 @@ extern "C" {
 #define HENTT_ETIMEOUT (-5)  /* a persistent batch tile gave up waiting (reported by hentt_batch_plan_status) */
 #define HENTT_EBUSY (-6)     /* a batch plan still has live graphs (hentt_batch_plan_set_grid / _destroy) */
 #define HENTT_ENONCANON (-7) /* hentt_check_canonical found input words outside [0, q) */
+#define HENTT_ESCRATCH (-8)  /* hentt_ct_tensor_noalloc: workspace beyond HENTT_NOALLOC_SCRATCH_WORDS */
 
 #define HENTT_LOG_N_MIN 6
 #define HENTT_LOG_N_MAX 17
@@ -202,6 +203,25 @@ int hentt_polymul(const hentt_tables *t, const uint64_t *a, const uint64_t *b, u
  * words from the library's pool. */
 int hentt_ct_tensor(const hentt_tables *t, const uint64_t *c, const uint64_t *d, uint64_t *out, uint32_t batch,
                     uint32_t flags, void *stream);
+
+/* For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * product as hentt_ct_tensor, with the same arguments, layout, flags and
+ * results, that allocates nothing.  The forward column pass of a two-pass
+ * product (coefficient-domain inputs, N > 2^12) writes its workspace of
+ * 4 batch limbs N words into a static device array of
+ * HENTT_NOALLOC_SCRATCH_WORDS words (64 MiB) that every GPU the library runs
+ * on holds until the process ends; a call needing more returns
+ * HENTT_ESCRATCH before enqueuing anything (e.g. one ciphertext pair of
+ * N = 2^16 at 32 limbs fits, two do not).  Every call on one GPU shares that
+ * array: calls that overlap in time on one GPU (different streams, or
+ * threads) race and must be serialised by the caller.  Kernel timing
+ * (hentt_prof_enable) does not cover this call.  No hipMalloc, hipFree or
+ * other allocating routine is called; the array's device address is looked
+ * up once per device on the first call. */
+#define HENTT_NOALLOC_SCRATCH_WORDS (8ull << 20)
+int hentt_ct_tensor_noalloc(const hentt_tables *t, const uint64_t *c, const uint64_t *d, uint64_t *out,
+                            uint32_t batch, uint32_t flags, void *stream);
 
 /* One polynomial set of an uneven batch: data [batch][limbs][N] in place,
  * transformed with the first `limbs` moduli of `t` (limbs <= t's limbs). */

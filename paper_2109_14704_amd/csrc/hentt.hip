@@ -92,6 +92,7 @@ void pool_put(void *p) {
 
 // ------------------------------------------------------------ launch timing
 std::atomic<bool> g_prof_on{false};
+thread_local bool g_timer_off = false;
 namespace {
 struct ProfRec {
   std::string name;
@@ -481,6 +482,7 @@ const char *hentt_status_str(int s) {
     case HENTT_ETIMEOUT: return "a batch tile waited past its spin limit (results incomplete)";
     case HENTT_EBUSY: return "the plan has live graphs (destroy them first)";
     case HENTT_ENONCANON: return "input words outside [0, q)";
+    case HENTT_ESCRATCH: return "the call needs more workspace than the static scratch array holds";
     default: return "unknown status";
   }
 }

@@ -65,15 +65,23 @@ void pool_put(void *p);
 // ------------------------------------------------------------ launch timing
 // While enabled (hentt_prof_enable), every launch is bracketed by HIP events
 // recorded on its stream and filed under "name<log_n>".
+// A NoTimerScope turns the timing off on its thread (entry points that must
+// not create events).
 extern std::atomic<bool> g_prof_on;
+extern thread_local bool g_timer_off;
 void prof_record(const char *name, int log_n, hipEvent_t a, hipEvent_t b);
+struct NoTimerScope {
+  bool old;
+  NoTimerScope() : old(g_timer_off) { g_timer_off = true; }
+  ~NoTimerScope() { g_timer_off = old; }
+};
 struct LaunchTimer {
   hipEvent_t a = nullptr, b = nullptr;
   hipStream_t st;
   const char *name;
   int ln;
   LaunchTimer(const char *nm, int log_n, hipStream_t s) : st(s), name(nm), ln(log_n) {
-    if (g_prof_on.load(std::memory_order_relaxed) && hipEventCreate(&a) == hipSuccess &&
+    if (!g_timer_off && g_prof_on.load(std::memory_order_relaxed) && hipEventCreate(&a) == hipSuccess &&
         hipEventCreate(&b) == hipSuccess)
       (void)hipEventRecord(a, st);
   }
