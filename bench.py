@@ -392,7 +392,9 @@ def micro_rates(args):
         return None
     from paper_2109_14704_amd import microbench
     t0 = time.perf_counter()
-    r = microbench.measure_all()
+    detail = {}
+    r = microbench.measure_all(detail)
+    r["copy_variants_gbs"] = detail
     print("bench: measured rates %s (%.1f s)" % (json.dumps(r), time.perf_counter() - t0), file=sys.stderr,
           flush=True)
     return r

@@ -20,9 +20,25 @@ namespace {
 
 typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
 
+// Copy of n 16-byte vectors: each workgroup moves chunks of 4 x 256
+// vectors (four independent loads in flight per lane), grid-stride over the
+// chunks, a guarded tail.  NT: streaming (non-temporal) loads and stores.
+template <bool NT>
 __global__ __launch_bounds__(256) void mb_copy_k(const u64x2 *__restrict__ src, u64x2 *__restrict__ dst, uint64_t n) {
-  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256)
-    __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+  const uint64_t chunks = n / 1024;
+  for (uint64_t c = blockIdx.x; c < chunks; c += gridDim.x) {
+    const uint64_t base = c * 1024 + threadIdx.x;
+    u64x2 v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = NT ? __builtin_nontemporal_load(src + base + 256 * k) : src[base + 256 * k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (NT) __builtin_nontemporal_store(v[k], dst + base + 256 * k);
+      else dst[base + 256 * k] = v[k];
+    }
+  }
+  for (uint64_t i = chunks * 1024 + (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256)
+    dst[i] = src[i];
 }
 
 __global__ __launch_bounds__(256) void mb_read_k(const u64x2 *__restrict__ src, uint64_t n, uint64_t *out) {
@@ -95,11 +111,16 @@ __global__ __launch_bounds__(256) void mb_issue_k(uint64_t *out, uint32_t iters,
 
 extern "C" {
 
-// Copies `bytes` (a multiple of 16) from src to dst on `stream`.
-int mb_copy(void *dst, const void *src, uint64_t bytes, uint32_t grid, void *stream) {
+// Copies `bytes` (a multiple of 16) from src to dst on `stream`; streaming
+// (non-temporal) accesses when nt.
+int mb_copy(void *dst, const void *src, uint64_t bytes, uint32_t grid, int nt, void *stream) {
   if (!dst || !src || bytes % 16 || grid == 0) return -1;
-  hipLaunchKernelGGL(mb_copy_k, dim3(grid), dim3(256), 0, (hipStream_t)stream, (const u64x2 *)src, (u64x2 *)dst,
-                     bytes / 16);
+  if (nt)
+    hipLaunchKernelGGL(mb_copy_k<true>, dim3(grid), dim3(256), 0, (hipStream_t)stream, (const u64x2 *)src,
+                       (u64x2 *)dst, bytes / 16);
+  else
+    hipLaunchKernelGGL(mb_copy_k<false>, dim3(grid), dim3(256), 0, (hipStream_t)stream, (const u64x2 *)src,
+                       (u64x2 *)dst, bytes / 16);
   return hipGetLastError() == hipSuccess ? 0 : -4;
 }
 

@@ -4,7 +4,8 @@ built from (csrc/microbench.hip, built into libhentt_mb.so).
 
 All rates come from HIP events on torch's current stream around launches of
 known work:
-  * hbm_copy: each byte of a 4 GiB buffer read once and written once;
+  * hbm_copy: each byte of a 4 GiB buffer read once and written once (the
+    best of streaming and ordinary accesses over a few grid sizes);
   * hbm_read: each byte read once;
   * mad64 / mulhi / mullo / add: lane-operations per second of
     v_mad_u64_u32, v_mul_hi_u32, v_mul_lo_u32, v_add_u32;
@@ -33,7 +34,7 @@ def lib():
             raise RuntimeError("libhentt_mb.so is not built; run __graft_entry__.build()")
         L = ctypes.CDLL(LIB_PATH)
         VP, U32, U64 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64
-        L.mb_copy.argtypes = [VP, VP, U64, U32, VP]
+        L.mb_copy.argtypes = [VP, VP, U64, U32, ctypes.c_int, VP]
         L.mb_read.argtypes = [VP, U64, VP, U32, VP]
         L.mb_issue.argtypes = [ctypes.c_int, VP, U32, U32, U32, U64, U64, U64, VP]
         for f in (L.mb_copy, L.mb_read, L.mb_issue):
@@ -62,18 +63,28 @@ def _cus():
     return torch.cuda.get_device_properties(0).multi_processor_count
 
 
-def hbm_copy_gbs(nbytes=4 << 30, reps=5):
-    src = torch.ones(nbytes // 8, dtype=torch.int64, device="cuda")
+def hbm_copy_gbs(nbytes=4 << 30, reps=5, detail=None):
+    """Best copy rate (bytes read + written per second) over streaming and
+    ordinary accesses and a few grid sizes; `detail` (a dict) receives every
+    configuration's rate."""
+    src = torch.arange(nbytes // 8, dtype=torch.int64, device="cuda")
     dst = torch.empty_like(src)
-    grid = _cus() * 8
     L = lib()
+    best = 0.0
+    for nt in (1, 0):
+        for per_cu in (4, 8, 16):
+            grid = _cus() * per_cu
 
-    def run():
-        assert L.mb_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nbytes, grid, _stream()) == 0
+            def run():
+                assert L.mb_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nbytes, grid, nt,
+                                 _stream()) == 0
 
-    s = _timed(run, reps)
-    assert torch.equal(src[:1024], dst[:1024]) and torch.equal(src[-1024:], dst[-1024:])
-    return 2 * nbytes / s / 1e9
+            gbs = 2 * nbytes / _timed(run, reps) / 1e9
+            if detail is not None:
+                detail["copy_%s_%dpercu" % ("nt" if nt else "plain", per_cu)] = round(gbs, 1)
+            best = max(best, gbs)
+    assert torch.equal(src, dst)
+    return best
 
 
 def hbm_read_gbs(nbytes=4 << 30, reps=5):
@@ -106,9 +117,9 @@ def issue_rate(kind, iters=None, reps=3):
     return grid * 256 * 8 * iters / s
 
 
-def measure_all():
+def measure_all(detail=None):
     r = {
-        "hbm_copy_gbs": hbm_copy_gbs(),
+        "hbm_copy_gbs": hbm_copy_gbs(detail=detail),
         "hbm_read_gbs": hbm_read_gbs(),
         "mad64_tops": issue_rate(MB_MAD64) / 1e12,
         "mulhi_tops": issue_rate(MB_MULHI) / 1e12,
