@@ -463,9 +463,11 @@ def bench_micro(args):
 def bench_ladder(args):
     """The kernel-design ladder of the paper's NTT evaluation on its own shape:
     forward transforms of [1024][8][2^15] (8 primes of 55 bits) by the naive
-    radix-2 design, staged designs with radix-2/4/8/16 LDS rounds, and the
-    library's kernels.  Each design's time, speedup over naive, and VALU
-    roofline fraction (21 ops per butterfly)."""
+    radix-2 design, staged radix-2 designs with LDS rounds and with wave
+    shuffles for the smallest gaps (1, 2, 4 register slots), staged designs
+    with radix-4/8/16 LDS rounds, and the library's kernels.  Each design's
+    time, speedup over naive, and roofline fractions (compulsory bytes and
+    multiplies; VALU issue beside them)."""
     import torch
     import workloads
     import paper_2109_14704_amd as H
@@ -484,6 +486,9 @@ def bench_ladder(args):
     one = R.Work(16.0 * coeffs) + tw
     designs = [(H.VARIANT_NAIVE, "naive radix-2, one global-memory launch per stage"),
                (H.VARIANT_STAGED_R2, "4 naive global stages + LDS blocks of 2048, radix-2 rounds"),
+               (H.VARIANT_SIMD1, "SIMD(64,64): radix-2 LDS stages to gap 128, wave shuffles for gaps 64..1, 1 slot"),
+               (H.VARIANT_SIMD2, "SIMD(128,64): radix-2 LDS stages to gap 256, wave shuffles for gaps 128..1, 2 slots"),
+               (H.VARIANT_SIMD4, "SIMD(256,64): radix-2 LDS stages to gap 512, wave shuffles for gaps 256..1, 4 slots"),
                (H.VARIANT_STAGED_R4, "column pass + LDS blocks of 4096, radix-4 rounds"),
                (H.VARIANT_STAGED_R8, "column pass + LDS blocks of 4096, radix-8 rounds (the paper's best)"),
                (H.VARIANT_STAGED_R16, "column pass + LDS blocks of 4096, radix-16 rounds"),

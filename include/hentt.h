@@ -162,6 +162,17 @@ int hentt_relin(const hentt_tables *t, const uint64_t *c, const uint64_t *ksk, u
  *   HENTT_VARIANT_STAGED_R2  four naive global stages, then LDS blocks of
  *                            2048 coefficients with radix-2 rounds (one stage
  *                            per LDS exchange); log_n = 15 only;
+ *   HENTT_VARIANT_SIMD1, _SIMD2, _SIMD4
+ *                            staged radix-2 with the smallest gaps exchanged
+ *                            between the lanes of a wavefront (the SIMD
+ *                            shuffling of section III-B): four naive global
+ *                            stages, LDS blocks of 2048 coefficients with one
+ *                            radix-2 stage per LDS exchange down to a gap of
+ *                            128 S, then the stages with gaps 64 S .. 1 inside
+ *                            each wavefront, every lane holding S pairs
+ *                            (S = 1, 2, 4: the paper's one-, two- and four-slot
+ *                            SIMD variants on 64-wide wavefronts); log_n = 15
+ *                            only;
  *   HENTT_VARIANT_STAGED_R4, _R8, _R16
  *                            one radix-8 column pass, then LDS blocks of 4096
  *                            coefficients with radix-4, -8 or -16 rounds;
@@ -174,6 +185,9 @@ int hentt_relin(const hentt_tables *t, const uint64_t *c, const uint64_t *ksk, u
 #define HENTT_VARIANT_STAGED_R8 3
 #define HENTT_VARIANT_STAGED_R16 4
 #define HENTT_VARIANT_STAGED_R2 5
+#define HENTT_VARIANT_SIMD1 6
+#define HENTT_VARIANT_SIMD2 7
+#define HENTT_VARIANT_SIMD4 8
 int hentt_ntt_fwd_variant(const hentt_tables *t, uint64_t *x, uint32_t batch, int variant, void *stream);
 
 /* Inverse negacyclic NTT in place: bit-reversed NTT domain -> natural order,

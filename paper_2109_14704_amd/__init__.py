@@ -296,6 +296,7 @@ def relin(tables, c, ksk, out=None, stream=None):
 # Kernel designs of hentt_ntt_fwd_variant (the ladder of section III-B).
 VARIANT_LIBRARY, VARIANT_NAIVE, VARIANT_STAGED_R4, VARIANT_STAGED_R8, VARIANT_STAGED_R16, VARIANT_STAGED_R2 = \
     0, 1, 2, 3, 4, 5
+VARIANT_SIMD1, VARIANT_SIMD2, VARIANT_SIMD4 = 6, 7, 8     # wave-shuffle stages, 1, 2 or 4 register slots per lane
 
 
 def ntt_fwd_variant(tables, x, variant, stream=None):

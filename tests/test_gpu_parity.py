@@ -115,10 +115,12 @@ def test_fused_product_shapes(gpu, log_n, batch, limbs):
         assert np.array_equal(host(H.ct_tensor(t, dev(c, gpu), dev(d, gpu))), want)
 
 
-@pytest.mark.parametrize("log_n,variant", [(6, 1), (12, 1), (15, 1), (17, 1), (15, 5), (15, 2), (15, 3), (15, 4), (15, 0)])
+@pytest.mark.parametrize("log_n,variant", [(6, 1), (12, 1), (15, 1), (17, 1), (15, 5), (15, 2), (15, 3), (15, 4), (15, 0),
+                                           (15, 6), (15, 7), (15, 8)])
 def test_design_ladder_variants(gpu, log_n, variant):
-    """Every kernel design of the ladder (naive radix-2, staged radix-2/4/8/16)
-    gives the forward transform word for word."""
+    """Every kernel design of the ladder (naive radix-2, staged radix-2, the
+    wave-shuffle SIMD variants with 1, 2 and 4 register slots, staged
+    radix-4/8/16) gives the forward transform word for word."""
     import paper_2109_14704_amd as H
     print("case ladder variant=%d log_n=%d" % (variant, log_n), flush=True)
     rng = np.random.default_rng(400 + 10 * log_n + variant)
@@ -134,7 +136,7 @@ def test_design_ladder_rejects(gpu):
     mods = CHAIN[:1]
     x = dev(rand_limbs(np.random.default_rng(1), (1, 1, 1 << 14), mods), gpu)
     t = H.Tables(14, mods)
-    for variant in (H.VARIANT_STAGED_R8, H.VARIANT_STAGED_R2, 7, -1):
+    for variant in (H.VARIANT_STAGED_R8, H.VARIANT_STAGED_R2, H.VARIANT_SIMD1, H.VARIANT_SIMD4, 9, -1):
         with pytest.raises(H.HenttError):
             H.ntt_fwd_variant(t, x, variant)
 
