@@ -66,13 +66,21 @@ def _tuned_grid(plan, grid_arg, data):
     return autotune.persistent_grid(plan, data)
 
 
-def _work_products(info, n_in, n_out, prod_muls, prod_valu):
-    """Per-kernel algorithmic work of a fused product step (polymul or tensor)."""
+def _tuned_kernels(op, t, step, data, units, info):
+    """The autotuner's kernel instance for the workload's shape (cached per
+    GPU architecture and kernel sources); recorded in the config."""
+    from paper_2109_14704_amd import autotune
+    info["kernel_instance"] = autotune.kernel_config(op, t, step, data, units)
+
+
+def _work_products(info, op, units, n_in, n_out, prod_muls, prod_valu):
+    """Per-kernel algorithmic work of a fused product step (polymul or tensor),
+    for the kernel instance the call runs."""
     import paper_2109_14704_amd as H
     from paper_2109_14704_amd import roofline as R
     n, L = info["N"], info["limbs"]
     logn = n.bit_length() - 1
-    pec = H.stage_split(logn)[1]
+    pec = H.tune_describe(op, logn, H.tune_get(op, logn, H.shape_class(units)), cols=True)[1]
     tw = lambda polys, st: R.transform_work(n, polys * L, st)
 
     def kernel(name):
@@ -109,7 +117,8 @@ def setup(name, torch, H, grid_arg=0):
 
         info = {"workload": "ckks_level", "N": n, "limbs": L, "polys_per_operand": polys,
                 "ops": "fwd(A), fwd(B), dyadic, inv (fused polymul)"}
-        kw, sw = _work_products(info, 2 * polys, polys, R.MUL_PROD * polys * L * n, R.VALU_PROD * polys * L * n)
+        _tuned_kernels("polymul", t, step, [out], polys * L, info)
+        kw, sw = _work_products(info, "polymul", polys * L, 2 * polys, polys, R.MUL_PROD * polys * L * n, R.VALU_PROD * polys * L * n)
         return dict(step=step, per_poly=per_poly_step, coeffs=3 * polys * L * n, info=info, kernel_work=kw,
                     step_work=sw, cpu=lambda k: cpu_ckks(w, k), cpu1=lambda k: cpu_ckks(w, k, threads=1),
                     sample_limit=polys, keep=(t, A, B, out))
@@ -129,7 +138,8 @@ def setup(name, torch, H, grid_arg=0):
 
         info = {"workload": "ct_tensor", "N": n, "limbs": L, "ct_pairs": pairs,
                 "ops": "fwd of c0,c1,d0,d1; tensor (c0d0, c0d1+c1d0, c1d1); inv of 3 outputs"}
-        kw, sw = _work_products(info, 4 * pairs, 3 * pairs, R.MUL_TENSOR * pairs * L * n,
+        _tuned_kernels("tensor", t, step, [out], pairs * L, info)
+        kw, sw = _work_products(info, "tensor", pairs * L, 4 * pairs, 3 * pairs, R.MUL_TENSOR * pairs * L * n,
                                 R.VALU_TENSOR * pairs * L * n)
         return dict(step=step, per_poly=per_poly_step, coeffs=7 * pairs * L * n, info=info, kernel_work=kw,
                     step_work=sw, cpu=lambda k: cpu_tensor(w, k), sample_limit=pairs, ctmul=pairs,

@@ -319,6 +319,34 @@ int hentt_prof_get(uint32_t i, char *name, uint32_t name_len, double *total_ms, 
  * workgroup.  Host-only, no device work. */
 int hentt_stage_split(uint32_t log_n, uint32_t *transform_cols, uint32_t *product_cols);
 
+/* Autotuning (the tuning constants of section III-B, chosen by measurement):
+ * every operation has, per N, a list of compiled kernel instances -- the
+ * stage split between the column pass and the block pass, and the words
+ * held per lane (the radix of the register rounds) -- of which instance 0 is
+ * the default.  A selection applies per (operation, N, shape class) to every
+ * later call of the library in this process (all threads); the shape class
+ * of a call groups its number of (batch entry, limb) units, batch * limbs:
+ * class 0 below 64, class 1 below 1024, class 2 above.  Every instance gives
+ * the same results (bit-exact); only its speed differs.  Products select
+ * among their instances only in the fused coefficient-to-coefficient form
+ * (the other forms run instance 0).  Host-only, no device work:
+ *   count: number of instances of op at N = 2^log_n;
+ *   describe: text of instance `choice` (copied into buf) and, if
+ *     column_stages is not null, the stages of its column pass (0: the whole
+ *     operation runs in one kernel per (batch entry, limb));
+ *   class: the shape class of `units` units;
+ *   select / get: the instance used for (op, N, class).
+ * HENTT_EINVAL for an unknown op, log_n out of range, or choice >= count. */
+#define HENTT_OP_FWD 0
+#define HENTT_OP_INV 1
+#define HENTT_OP_POLYMUL 2
+#define HENTT_OP_TENSOR 3
+int hentt_tune_count(int op, uint32_t log_n, uint32_t *count);
+int hentt_tune_describe(int op, uint32_t log_n, uint32_t choice, char *buf, uint32_t len, uint32_t *column_stages);
+int hentt_tune_class(uint64_t units, uint32_t *cls);
+int hentt_tune_select(int op, uint32_t log_n, uint32_t cls, uint32_t choice);
+int hentt_tune_get(int op, uint32_t log_n, uint32_t cls, uint32_t *choice);
+
 /* Text for a status code (static storage). */
 const char *hentt_status_str(int status);
 

@@ -14,7 +14,7 @@ import torch
 __all__ = ["HenttError", "Tables", "ntt_fwd", "ntt_inv", "dyadic_mul", "polymul", "ct_tensor", "ntt_batch",
            "psi", "lib", "LIB_PATH", "prof_enable", "prof_read", "BatchPlan", "stage_split", "ntt_fwd_variant",
            "rescale", "ct_matmul", "relin", "check_canonical", "ntt_batch_status", "pool_bytes", "pool_trim",
-           "NonCanonicalError"]
+           "NonCanonicalError", "tune_count", "tune_describe", "shape_class", "tune_select", "tune_get", "TUNE_OPS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("HENTT_LIB") or os.path.join(_HERE, "libhentt.so")  # HENTT_LIB: alternative build
@@ -80,6 +80,11 @@ def lib():
             "hentt_graph_launch": [_VP, _VP],
             "hentt_graph_destroy": [_VP],
             "hentt_stage_split": [_U32, ctypes.POINTER(_U32), ctypes.POINTER(_U32)],
+            "hentt_tune_count": [ctypes.c_int, _U32, ctypes.POINTER(_U32)],
+            "hentt_tune_describe": [ctypes.c_int, _U32, _U32, ctypes.c_char_p, _U32, ctypes.POINTER(_U32)],
+            "hentt_tune_class": [_U64, ctypes.POINTER(_U32)],
+            "hentt_tune_select": [ctypes.c_int, _U32, _U32, _U32],
+            "hentt_tune_get": [ctypes.c_int, _U32, _U32, ctypes.POINTER(_U32)],
             "hentt_prof_enable": [ctypes.c_int],
             "hentt_prof_count": [],
             "hentt_prof_get": [_U32, ctypes.c_char_p, _U32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_U32)],
@@ -146,6 +151,47 @@ def stage_split(log_n):
     a, b = _U32(), _U32()
     _check(lib().hentt_stage_split(log_n, ctypes.byref(a), ctypes.byref(b)), "hentt_stage_split")
     return a.value, b.value
+
+
+# Operations with tunable kernel instances (hentt_tune_*).
+TUNE_OPS = {"fwd": 0, "inv": 1, "polymul": 2, "tensor": 3}
+
+
+def _op(op):
+    return TUNE_OPS[op] if isinstance(op, str) else int(op)
+
+
+def tune_count(op, log_n):
+    """Number of compiled kernel instances of op ("fwd", "inv", "polymul", "tensor") at N = 2^log_n."""
+    n = _U32()
+    _check(lib().hentt_tune_count(_op(op), log_n, ctypes.byref(n)), "hentt_tune_count")
+    return n.value
+
+
+def tune_describe(op, log_n, choice, cols=False):
+    """Text of instance `choice`; with cols=True, (text, column-pass stages)."""
+    buf = ctypes.create_string_buffer(128)
+    c = _U32()
+    _check(lib().hentt_tune_describe(_op(op), log_n, choice, buf, 128, ctypes.byref(c)), "hentt_tune_describe")
+    return (buf.value.decode(), c.value) if cols else buf.value.decode()
+
+
+def shape_class(units):
+    """The library's shape class of a call over `units` (batch x limbs) units."""
+    c = _U32()
+    _check(lib().hentt_tune_class(int(units), ctypes.byref(c)), "hentt_tune_class")
+    return c.value
+
+
+def tune_select(op, log_n, cls, choice):
+    """Use instance `choice` for op at N = 2^log_n and shape class `cls` from now on."""
+    _check(lib().hentt_tune_select(_op(op), log_n, cls, choice), "hentt_tune_select")
+
+
+def tune_get(op, log_n, cls):
+    c = _U32()
+    _check(lib().hentt_tune_get(_op(op), log_n, cls, ctypes.byref(c)), "hentt_tune_get")
+    return c.value
 
 
 def psi(q, log_n):

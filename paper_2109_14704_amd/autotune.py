@@ -138,7 +138,8 @@ def kernel_config(op, tables, run, data, batch_units, check=None, force=False):
     "tensor") at the tables' N and a (batch x limbs) shape class, among the
     instances the library was built with (cached).  run() performs the op on
     `data` in place; it is timed after every candidate's outputs equal the
-    default's.  Selects the choice in the library and returns its description."""
+    default's.  Selects the choice in the library and returns its description;
+    `data` is restored to its contents on entry."""
     import paper_2109_14704_amd as H
     cls = H.shape_class(batch_units)
     key = "kernel/%s/%s/%s/logn%d/%s" % (_arch(), source_digest(), op, tables.log_n, cls)
@@ -153,7 +154,8 @@ def kernel_config(op, tables, run, data, batch_units, check=None, force=False):
     def apply(i):
         H.tune_select(op, tables.log_n, cls, i)
 
-    best, table = _gated_choice(cands, apply, run, data, check, restore_every_run=True)
+    # timing repeats run() on its own outputs (any canonical words time the same)
+    best, table = _gated_choice(cands, apply, run, data, check, restore_every_run=False)
     H.tune_select(op, tables.log_n, cls, best)
     cache = _load()
     cache[key] = {"choice": best, "describe": H.tune_describe(op, tables.log_n, best),

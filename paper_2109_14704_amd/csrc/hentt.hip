@@ -835,6 +835,58 @@ int hentt_ntt_batch_status(const hentt_job *jobs, uint32_t njobs, int dir) {
   return plan_status(p.get());
 }
 
+namespace {
+int tune_count(int op, uint32_t log_n, uint32_t *count) {
+  if (op < 0 || op >= kTuneOps || log_n < HENTT_LOG_N_MIN || log_n > HENTT_LOG_N_MAX) return HENTT_EINVAL;
+  if (op == HENTT_OP_FWD || op == HENTT_OP_INV) *count = transform_candidates(log_n);
+  else (void)prod_candidates(op == HENTT_OP_POLYMUL ? PROD_MUL : PROD_TENSOR, log_n, count);
+  return HENTT_OK;
+}
+}  // namespace
+
+int hentt_tune_count(int op, uint32_t log_n, uint32_t *count) {
+  if (!count) return HENTT_EINVAL;
+  return tune_count(op, log_n, count);
+}
+
+int hentt_tune_describe(int op, uint32_t log_n, uint32_t choice, char *buf, uint32_t len, uint32_t *column_stages) {
+  uint32_t n = 0;
+  if (!buf || len == 0 || tune_count(op, log_n, &n) || choice >= n) return HENTT_EINVAL;
+  const char *d = nullptr;
+  uint32_t cols = 0;
+  if (op == HENTT_OP_FWD || op == HENTT_OP_INV) {
+    d = transform_describe(log_n, choice);
+    cols = transform_cols(log_n, choice);
+  } else {
+    const ProdCand &c = prod_candidates(op == HENTT_OP_POLYMUL ? PROD_MUL : PROD_TENSOR, log_n, &n)[choice];
+    d = c.desc;
+    cols = c.pec;
+  }
+  snprintf(buf, len, "%s", d);
+  if (column_stages) *column_stages = cols;
+  return HENTT_OK;
+}
+
+int hentt_tune_class(uint64_t units, uint32_t *cls) {
+  if (!cls) return HENTT_EINVAL;
+  *cls = tune_class(units);
+  return HENTT_OK;
+}
+
+int hentt_tune_select(int op, uint32_t log_n, uint32_t cls, uint32_t choice) {
+  uint32_t n = 0;
+  if (tune_count(op, log_n, &n) || choice >= n || cls >= (uint32_t)kTuneClasses) return HENTT_EINVAL;
+  g_choice[op][log_n][cls].store((uint8_t)choice);
+  return HENTT_OK;
+}
+
+int hentt_tune_get(int op, uint32_t log_n, uint32_t cls, uint32_t *choice) {
+  uint32_t n = 0;
+  if (!choice || tune_count(op, log_n, &n) || cls >= (uint32_t)kTuneClasses) return HENTT_EINVAL;
+  *choice = g_choice[op][log_n][cls].load();
+  return HENTT_OK;
+}
+
 int hentt_pool_trim(void) {
   std::lock_guard<std::mutex> lk(g_pool_mu);
   int cur = 0;

@@ -93,26 +93,32 @@ struct LaunchTimer {
   }
 };
 
-// ------------------------------------------------------------ launch plan
-// Stage split per N: transforms with N <= 2^14 run whole in one workgroup
-// (one HBM round trip); larger N run a column pass of EC stages then blocks
-// of 2^(log_n - EC) coefficients.  The column pass is HBM-bound with idle
-// ALU, so it takes 5 stages at N = 2^15 and 2^16, leaving 2^10 / 2^11 blocks
-// to the ALU-bound block and fused kernels (measured: 10% faster on the
-// CKKS-level batch and 19% on the ciphertext tensor than 3 / 4 stages).
-constexpr uint32_t kWholeMaxLogN = 14;  // largest transform done whole by one workgroup
-template <int LOGN> struct Plan {
-  static constexpr bool WHOLE = LOGN <= (int)kWholeMaxLogN;
-  static constexpr int EC = LOGN == 15 ? 5 : LOGN == 16 ? 5 : LOGN == 17 ? 4 : (LOGN > 12 ? LOGN - 12 : 1);
-  static constexpr int B = LOGN - EC;
-  // fused products: one kernel up to 2^12, else a column pass of PEC stages
-  // and blocks of 2^(LOGN - PEC) coefficients
-  static constexpr bool PROD_WHOLE = LOGN <= 12;
-  static constexpr int PEC = LOGN == 15 ? 5 : LOGN == 16 ? 5 : (LOGN > 12 ? LOGN - 12 : 1);
+// ------------------------------------------------------------ launch plans
+// Every operation has, per N, a list of compiled kernel instances (stage
+// split, words per lane); instance 0 is the measured default and the
+// autotuner may select another per (operation, N, shape class).  The shape
+// class groups the (batch entry, limb) units of a call: < 64, < 1024, more.
+constexpr int kTuneOps = 4;      // HENTT_OP_FWD, _INV, _POLYMUL, _TENSOR
+constexpr int kTuneClasses = 3;
+extern std::atomic<uint8_t> g_choice[kTuneOps][HENTT_LOG_N_MAX + 1][kTuneClasses];
+uint32_t tune_class(uint64_t units);
+uint32_t tune_choice(int op, uint32_t log_n, uint64_t units);
+uint32_t transform_candidates(uint32_t log_n);
+const char *transform_describe(uint32_t log_n, uint32_t choice);
+uint32_t transform_cols(uint32_t log_n, uint32_t choice);
+
+typedef void (*prod_fn)(const hentt_tables *, const ProdArgs &, uint32_t, bool, bool, uint64_t *, hipStream_t);
+struct ProdCand {
+  prod_fn fn;          // launch sequence (ws: the forward column pass's workspace, if pec > 0)
+  uint32_t pec;        // column stages of a two-pass product (0: one kernel)
+  const char *desc;
 };
-// Elements per lane (2^E) in the fused product kernels: the tensor keeps four
-// transformed inputs live, so it uses 8 per lane to stay within the VGPRs.
-template <int MODE> struct ProdE { static constexpr int E = MODE == PROD_MUL ? 4 : 3; };
+const ProdCand *prod_candidates(int mode, uint32_t log_n, uint32_t *count);
+const ProdCand *tensor_candidates(uint32_t log_n, uint32_t *count);
+// the instance a call runs: the tuned one for the fused coefficient-to-
+// coefficient form, the default otherwise
+const ProdCand &prod_select(int mode, uint32_t log_n, uint64_t units, bool fused);
+uint32_t product_default_cols(uint32_t log_n);
 
 inline ColArgs col_args(uint64_t *x, uint64_t sb) {
   ColArgs a{};
@@ -129,13 +135,9 @@ inline ColArgs col_args(uint64_t *x, uint64_t sb) {
 int run_transform(const hentt_tables *t, uint64_t *x, uint32_t batch, hipStream_t st, bool inv);
 void stage_split(uint32_t log_n, uint32_t *transform_cols, uint32_t *product_cols);
 // tr_prod_mul.hip / tr_prod_tensor.hip: products, fused with the transforms
-// when in_coeff / out_coeff.  ws: workspace for a two-pass product's forward
-// column pass (null: taken from the pool).
+// when in_coeff / out_coeff; the workspace comes from the pool.
 int run_prod(const hentt_tables *t, int mode, const ProdArgs &pa, uint32_t batch, bool in_coeff, bool out_coeff,
              hipStream_t st);
-bool prod_needs_ws(uint32_t log_n);
-void launch_prod_tensor(uint32_t log_n, const hentt_tables *t, const ProdArgs &pa, uint32_t batch, bool in_coeff,
-                        bool out_coeff, uint64_t *ws, hipStream_t st);
 // tr_he.hip
 int run_rescale(const hentt_tables *t, const uint64_t *c, uint64_t *out, uint32_t batch, bool ntt, hipStream_t st);
 int run_relin(const hentt_tables *t, const uint64_t *c, const uint64_t *ksk, uint64_t *out, uint32_t batch,

@@ -43,9 +43,17 @@ int rs_constants(Storage *s, uint32_t level, const RsLimb **out) {
   return HENTT_OK;
 }
 
+// Stage split of the rescale's forward transforms: the plain transform's
+// default (whole up to 2^14; 5 column stages at 2^15 and 2^16, 4 at 2^17).
+template <int LOGN> struct RsPlan {
+  static constexpr bool WHOLE = LOGN <= 14;
+  static constexpr int EC = LOGN == 15 ? 5 : LOGN == 16 ? 5 : LOGN == 17 ? 4 : (LOGN > 12 ? LOGN - 12 : 1);
+  static constexpr int B = LOGN - EC;
+};
+
 template <int LOGN> void launch_rescale_ntt(const RsArgs &a, const Storage *s, hipStream_t st) {
   const uint32_t units = a.batch * a.L;
-  using P = Plan<LOGN>;
+  using P = RsPlan<LOGN>;
   if constexpr (P::WHOLE) {
     LaunchTimer lt_("k_rs_whole", LOGN, st);
     hipLaunchKernelGGL((k_rs_whole<LOGN, 4>), dim3(units), dim3(1 << (LOGN - 4)), 0, st, a, s->d_tw, s->d_lc);

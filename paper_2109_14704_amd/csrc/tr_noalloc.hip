@@ -49,8 +49,9 @@ extern "C" int hentt_ct_tensor_noalloc(const hentt_tables *t, const uint64_t *c,
   const uintptr_t d0 = (uintptr_t)d, d1 = d0 + (uintptr_t)(2 * NL * batch * 8);
   if ((o0 < c1 && c0 < o1) || (o0 < d1 && d0 < o1)) return HENTT_EINVAL;
   const bool in_coeff = !(flags & HENTT_IN_NTT), out_coeff = !(flags & HENTT_OUT_NTT);
+  const ProdCand &cand = prod_select(PROD_TENSOR, ln, (uint64_t)batch * t->limbs, in_coeff && out_coeff);
   uint64_t *ws = nullptr;
-  if (in_coeff && prod_needs_ws(ln)) {
+  if (in_coeff && cand.pec > 0) {
     if (4 * NL * (uint64_t)batch > kScratchWords) return HENTT_ESCRATCH;
     int rc = scratch_ptr(&ws);
     if (rc) return rc;
@@ -66,7 +67,7 @@ extern "C" int hentt_ct_tensor_noalloc(const hentt_tables *t, const uint64_t *c,
   hipStream_t st = (hipStream_t)stream;
   {
     NoTimerScope quiet;  // launch timing would create events
-    launch_prod_tensor(ln, t, pa, batch, in_coeff, out_coeff, ws, st);
+    cand.fn(t, pa, batch, in_coeff, out_coeff, ws, st);
   }
   HIPCHK(hipGetLastError());
   return HENTT_OK;

@@ -1,15 +1,29 @@
-// Dispatch of the ciphertext tensor product (section II-A, Mul) at every N.
+// Compiled instances of the ciphertext tensor product (section II-A, Mul) at
+// every N; candidate 0 is the default and serves every domain combination.
 #include "prod_launch.hpp"
 
 namespace hentt_rt {
 namespace {
-#define TEN_ENTRY(n) launch_prod<n, PROD_TENSOR>,
-const prod_fn k_ten_table[] = {HENTT_SIZES(TEN_ENTRY)};
+#define D(n, pec) {launch_prod_cfg<n, PROD_TENSOR, pec, 3, true>, pec, "column stages " #pec ", block words per lane 2^3"}
+#define C(n, pec, e) {launch_prod_cfg<n, PROD_TENSOR, pec, e, false>, pec, "column stages " #pec ", block words per lane 2^" #e}
+const ProdCand t6[] = {D(6, 0)}, t7[] = {D(7, 0)}, t8[] = {D(8, 0)}, t9[] = {D(9, 0)}, t10[] = {D(10, 0)},
+               t11[] = {D(11, 0)}, t12[] = {D(12, 0)};
+const ProdCand t13[] = {D(13, 1), C(13, 0, 3)};
+const ProdCand t14[] = {D(14, 2), C(14, 3, 3)};
+const ProdCand t15[] = {D(15, 5), C(15, 4, 3), C(15, 5, 2)};
+const ProdCand t16[] = {D(16, 5), C(16, 4, 3), C(16, 5, 2)};
+const ProdCand t17[] = {D(17, 5), C(17, 4, 3)};
+#undef D
+#undef C
+const ProdList k_ten[] = {HENTT_PROD_LIST(t6),  HENTT_PROD_LIST(t7),  HENTT_PROD_LIST(t8),  HENTT_PROD_LIST(t9),
+                          HENTT_PROD_LIST(t10), HENTT_PROD_LIST(t11), HENTT_PROD_LIST(t12), HENTT_PROD_LIST(t13),
+                          HENTT_PROD_LIST(t14), HENTT_PROD_LIST(t15), HENTT_PROD_LIST(t16), HENTT_PROD_LIST(t17)};
 }  // namespace
 
-void launch_prod_tensor(uint32_t log_n, const hentt_tables *t, const ProdArgs &pa, uint32_t batch, bool in_coeff,
-                        bool out_coeff, uint64_t *ws, hipStream_t st) {
-  k_ten_table[log_n - HENTT_LOG_N_MIN](t, pa, batch, in_coeff, out_coeff, ws, st);
+const ProdCand *tensor_candidates(uint32_t log_n, uint32_t *count) {
+  const ProdList &l = k_ten[log_n - HENTT_LOG_N_MIN];
+  *count = l.n;
+  return l.c;
 }
 
 }  // namespace hentt_rt

@@ -99,3 +99,25 @@ def test_roofline_accounting_reproduces_table_one():
     # section IV-B: naive radix-2 density 1.5, staged radix-8 SLM density 8.9 at N = 32K
     assert roofline.paper_density("naive", 1 << 15) == pytest.approx(1.5)
     assert roofline.paper_density("radix8_slm", 1 << 15) == pytest.approx(8.906, abs=1e-3)
+
+
+def test_tuning_abi_host_only():
+    """The autotuner's instance lists and selections (host-only calls)."""
+    H, L = _lib()
+    assert H.tune_count("fwd", 12) == 1 and H.tune_count("fwd", 15) >= 3 and H.tune_count("tensor", 16) >= 2
+    # instance 0 of every op is the library's default stage split
+    for ln in range(6, 18):
+        tc, pc = H.stage_split(ln)
+        assert H.tune_describe("fwd", ln, 0, cols=True)[1] == tc
+        assert H.tune_describe("polymul", ln, 0, cols=True)[1] == pc
+    assert [H.shape_class(u) for u in (1, 63, 64, 1023, 1024, 10 ** 6)] == [0, 0, 1, 1, 2, 2]
+    H.tune_select("inv", 16, 1, 2)
+    assert H.tune_get("inv", 16, 1) == 2 and H.tune_get("inv", 16, 0) == 0 and H.tune_get("fwd", 16, 1) == 0
+    H.tune_select("inv", 16, 1, 0)
+    U32 = ctypes.c_uint32
+    c = U32()
+    assert L.hentt_tune_count(4, 15, ctypes.byref(c)) == -1            # unknown op
+    assert L.hentt_tune_count(0, 18, ctypes.byref(c)) == -1            # log_n out of range
+    assert L.hentt_tune_select(0, 15, 3, 0) == -1                      # no such class
+    assert L.hentt_tune_select(0, 15, 0, H.tune_count("fwd", 15)) == -1
+    assert L.hentt_tune_describe(0, 15, 0, None, 0, None) == -1
