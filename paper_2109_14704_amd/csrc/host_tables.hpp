@@ -49,7 +49,12 @@ inline bool is_prime(uint64_t n) {
   return true;
 }
 
-inline uint32_t brv(uint32_t x, int bits) { return bits == 0 ? 0u : __builtin_bitreverse32(x) >> (32 - bits); }
+// The low `bits` bits of x in reverse order.
+inline uint32_t brv(uint32_t x, int bits) {
+  uint32_t r = 0;
+  for (int i = 0; i < bits; ++i) r |= ((x >> i) & 1u) << (bits - 1 - i);
+  return r;
+}
 
 // Smallest primitive 2N-th root of unity mod q (q prime, q = 1 mod 2N): take
 // a root g of order exactly 2N (c = r^((q-1)/2N) for small bases r, accepted
