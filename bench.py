@@ -700,7 +700,8 @@ def bench_serving(args):
     import workloads
     from paper_2109_14704_amd import serve
     chain = workloads.moduli("serving")
-    be = serve.HipBackend(chain, streams=2)
+    budget = 24 << 30
+    be = serve.HipBackend(chain, streams=2, budget_bytes=budget)
     gen = torch.Generator(device="cuda:0")
     ops = {}
 
@@ -719,7 +720,6 @@ def bench_serving(args):
     def requests(trace):
         return [serve.Request(i, t, ln, lvl, *operands(ln, lvl, i % 2)) for i, (t, ln, lvl) in enumerate(trace)]
 
-    budget = 24 << 30
     warm = 200
     n = args.requests
     # saturation: every request offered at t = 0
@@ -749,12 +749,16 @@ def bench_serving(args):
         print("bench: load %.2f server p50 %.3f p99 %.3f ms; per-request p50 %.3f p99 %.3f ms" % (
             f, srv.get("p50_ms", -1), srv.get("p99_ms", -1), base.get("p50_ms", -1), base.get("p99_ms", -1)),
             file=sys.stderr, flush=True)
+    memory = {"budget_bytes": budget, "peak_held_bytes": be.peak_held,
+              "held_bytes_at_end": be.held_bytes(), "torch_peak_reserved_bytes": torch.cuda.max_memory_reserved(),
+              "note": "held = operand slabs + the library's workspace pool; the footprint admitted per request is "
+                      "88 L N bytes (7 slab polynomials + 4 workspace polynomials)"}
     result = {"metric": METRIC, "value": round(sat, 1), "unit": "ct-mul/s", "n_gpus": 1, "steps": n,
               "warmup": warm, "ms_per_step": round(1e3 / sat, 4), "higher_is_better": True, "scaling": "weak",
               "vs_baseline": None, "dtype": "u64", "data": "synthetic",
               "config": {"workload": "serving", "N": [1 << 14, 1 << 15, 1 << 16], "levels": [4, 24],
                          "hbm_budget_bytes": budget, "streams": 2, "requests": n},
-              "latency": rows}
+              "latency": rows, "memory": memory}
     print(json.dumps(result), flush=True)
 
 

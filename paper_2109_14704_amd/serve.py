@@ -2,15 +2,22 @@
 section II-A) over requests of mixed N and level.
 
 Requests arrive over time (Poisson traces in the benchmark).  The scheduler
-admits a request when its HBM footprint fits the budget (56 L N bytes: two
-input ciphertexts of 2 polynomials and the 3-polynomial tensor output, L
-limbs of N words), groups the admitted requests of equal (N, level) into one
-batched call, and keeps up to `streams` steps in flight on separate streams,
-so requests that arrive while earlier ones run join the next step as soon as
-a stream and memory free up.  Operand slabs come from a capacity-reusing
-pool (the memory cache of section III-C-1).  Latency = completion of the
-request's step minus its arrival; completion is observed with stream events,
-the only host synchronisation.
+admits a request when its HBM footprint fits the budget, groups the
+admitted requests of equal (N, level) into one batched call, and keeps up to
+`streams` steps in flight on separate streams, so requests that arrive while
+earlier ones run join the next step as soon as a stream and memory free up.
+
+The footprint is what a request makes the device hold while it is in
+flight: 88 L N bytes for L limbs of N words -- its two input ciphertexts (4
+polynomials) and the 3-polynomial tensor output in the step's slab, plus the
+4 polynomials of the library's forward-column-pass workspace.  The GPU
+backend keeps what it holds within the budget: slabs are sized exactly to
+their step and pooled for reuse (the memory cache of section III-C-1), idle
+slabs are freed before a new one would take the slab total past its share
+of the budget, and the library's workspace pool is trimmed when it holds
+more than its share.  Latency = completion of the request's step minus its
+arrival; completion is observed with stream events, the only host
+synchronisation.
 
 The scheduling logic is backend-independent: HipBackend runs on the GPU
 through the library's C ABI; the unit tests drive the same scheduler with a
@@ -24,9 +31,13 @@ import numpy as np
 WORD = 8
 
 
+SLAB_POLYS = 7       # c, d (2 polynomials each) and the tensor output (3)
+WORKSPACE_POLYS = 4  # the library's forward column pass over c0, c1, d0, d1
+
+
 def footprint(log_n, level):
-    """HBM bytes a request holds while admitted: c, d (2 polys each) + out (3 polys)."""
-    return 7 * level * (1 << log_n) * WORD
+    """HBM bytes a request makes the device hold while it is admitted."""
+    return (SLAB_POLYS + WORKSPACE_POLYS) * level * (1 << log_n) * WORD
 
 
 class Request:
@@ -190,20 +201,29 @@ def latency_stats(reqs):
 
 # ============================================================ GPU backend
 class HipBackend:
-    """Steps on the GPU: each (N, level) group is gathered into a pooled slab
+    """Steps on the GPU: each (N, level) group is gathered into a slab
     (device-to-device copies stand in for the upload of the ciphertexts) and
-    multiplied by one hentt_ct_tensor call; one stream per in-flight step."""
+    multiplied by one hentt_ct_tensor call; one stream per in-flight step.
 
-    def __init__(self, chain, log_ns=(14, 15, 16), streams=2, verify=False):
+    budget_bytes bounds what the backend holds: slabs up to the slab share
+    (7/11) of it, the library's workspace pool up to the workspace share
+    (4/11).  held_bytes() reports both; peak_held the largest value seen."""
+
+    def __init__(self, chain, log_ns=(14, 15, 16), streams=2, verify=False, budget_bytes=None):
         import torch
         import paper_2109_14704_amd as H
         self.torch, self.H = torch, H
         self.tables = {ln: H.Tables(ln, chain) for ln in log_ns}
         self.views = {}
         self.streams = [torch.cuda.Stream() for _ in range(streams)]
-        self.pool = collections.defaultdict(list)   # (log_n, level) -> free slabs [cap, c, d, out]
+        self.pool = collections.OrderedDict()   # (log_n, level, count) -> free slabs [c, d, out], oldest first
         self.keep_results = verify
         self.launches = 0
+        share = SLAB_POLYS + WORKSPACE_POLYS
+        self.slab_cap = None if budget_bytes is None else budget_bytes * SLAB_POLYS // share
+        self.ws_cap = None if budget_bytes is None else budget_bytes * WORKSPACE_POLYS // share
+        self.slab_bytes = 0                      # every slab allocated and not freed, busy or idle
+        self.peak_held = 0
 
     def view(self, log_n, level):
         key = (log_n, level)
@@ -211,16 +231,35 @@ class HipBackend:
             self.views[key] = self.tables[log_n].view(level)
         return self.views[key]
 
+    def held_bytes(self):
+        return self.slab_bytes + self.H.pool_bytes()
+
+    def _free_idle(self, need):
+        """Free idle slabs, oldest first, until `need` more bytes fit the slab share."""
+        while self.slab_cap is not None and self.slab_bytes + need > self.slab_cap:
+            key = next((k for k, v in self.pool.items() if v), None)
+            if key is None:
+                break
+            slab = self.pool[key].pop(0)
+            self.slab_bytes -= sum(t.numel() * WORD for t in slab)
+            if not self.pool[key]:
+                del self.pool[key]
+
     def _slab(self, log_n, level, count):
+        free = self.pool.get((log_n, level, count))
+        if free:
+            slab = free.pop(0)
+            if not free:
+                del self.pool[(log_n, level, count)]
+            return slab
         torch = self.torch
-        free = self.pool[(log_n, level)]
-        for i, s in enumerate(free):
-            if s[0] >= count:                    # any free slab with enough capacity
-                return free.pop(i)
-        cap = max(count, 4)
         n = 1 << log_n
-        mk = lambda k: torch.empty((cap, k, level, n), dtype=torch.int64, device="cuda:0")
-        return [cap, mk(2), mk(2), mk(3)]
+        need = SLAB_POLYS * count * level * n * WORD
+        self._free_idle(need)
+        mk = lambda k: torch.empty((count, k, level, n), dtype=torch.int64, device="cuda:0")
+        slab = [mk(2), mk(2), mk(3)]
+        self.slab_bytes += need
+        return slab
 
     def launch(self, batch, slot=0):
         torch, H = self.torch, self.H
@@ -231,16 +270,16 @@ class HipBackend:
         with torch.cuda.stream(st):
             for (log_n, level), rs in batch:
                 slab = self._slab(log_n, level, len(rs))
-                cap, c, d, out = slab
+                c, d, out = slab
                 for i, r in enumerate(rs):
                     c[i].copy_(r.c[0], non_blocking=True)
                     d[i].copy_(r.d[0], non_blocking=True)
                     r.slot = (slab, i)
-                b = len(rs)
-                H.ct_tensor(self.view(log_n, level), c[:b], d[:b], out=out[:b], stream=st)
-                used.append(((log_n, level), slab))
+                H.ct_tensor(self.view(log_n, level), c, d, out=out, stream=st)
+                used.append(((log_n, level, len(rs)), slab))
             ev = torch.cuda.Event()
             ev.record(st)
+        self.peak_held = max(self.peak_held, self.held_bytes())
         return (ev, used, st)
 
     def poll(self, handle):
@@ -250,11 +289,14 @@ class HipBackend:
         if self.keep_results:
             for r in reqs:
                 slab, i = r.slot
-                r.result = slab[3][i:i + 1].clone()
+                r.result = slab[2][i:i + 1].clone()
 
     def release(self, handle):
         for key, slab in handle[1]:
-            self.pool[key].append(slab)
+            self.pool.setdefault(key, []).append(slab)
+            self.pool.move_to_end(key)
+        if self.ws_cap is not None and self.H.pool_bytes() > self.ws_cap:
+            self.H.pool_trim()                  # frees idle workspace buffers (waits for their streams)
 
 
 def serve_per_request(requests, backend, clock=time.perf_counter):
@@ -271,12 +313,12 @@ def serve_per_request(requests, backend, clock=time.perf_counter):
         r.arrival = t0 + r.arrival
         with torch.cuda.stream(st):
             slab = backend._slab(r.log_n, r.level, 1)
-            cap, c, d, out = slab
+            c, d, out = slab
             c[0].copy_(r.c[0], non_blocking=True)
             d[0].copy_(r.d[0], non_blocking=True)
-            H.ct_tensor(backend.view(r.log_n, r.level), c[:1], d[:1], out=out[:1], stream=st)
+            H.ct_tensor(backend.view(r.log_n, r.level), c, d, out=out, stream=st)
         st.synchronize()
         r.t_done = clock()
         r.state = "done"
-        backend.pool[(r.log_n, r.level)].append(slab)
+        backend.pool.setdefault((r.log_n, r.level, 1), []).append(slab)
     return clock() - t0

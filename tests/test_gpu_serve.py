@@ -16,7 +16,8 @@ def test_served_results_match_alone_and_oracle(gpu):
     from paper_2109_14704_amd import serve
     print("case serving mix", flush=True)
     chain = workloads.moduli("serving")
-    be = serve.HipBackend(chain, streams=2, verify=True)
+    budget = serve.footprint(16, 12) * 6
+    be = serve.HipBackend(chain, streams=2, verify=True, budget_bytes=budget)
     trace = workloads.serving_trace(36, rate_per_s=3000.0, seed_stream=7)
     reqs, host_ops = [], {}
     for i, (t, ln, lvl) in enumerate(trace):
@@ -25,11 +26,12 @@ def test_served_results_match_alone_and_oracle(gpu):
         host_ops[i] = (c, d)
         reqs.append(serve.Request(i, t, ln, lvl, torch.from_numpy(c.view(np.int64)).cuda(),
                                   torch.from_numpy(d.view(np.int64)).cuda()))
-    sched = serve.Scheduler(be, budget_bytes=serve.footprint(16, 12) * 6, streams=2)
+    sched = serve.Scheduler(be, budget_bytes=budget, streams=2)
     sched.run_trace(reqs)
     torch.cuda.synchronize()
     assert all(r.state == "done" for r in reqs), [(r.rid, r.state, r.error) for r in reqs if r.state != "done"]
     assert sched.steps >= 2 and sched.reserved == 0
+    assert 0 < be.peak_held <= budget, (be.peak_held, budget)       # slabs + library workspace within the budget
     for r in reqs:
         alone = H.ct_tensor(be.view(r.log_n, r.level), r.c, r.d)
         assert torch.equal(alone, r.result), r.rid
@@ -71,7 +73,8 @@ def test_served_mix_all_levels(gpu):
     from paper_2109_14704_amd import serve
     print("case serving mix, all levels", flush=True)
     chain = workloads.moduli("serving")
-    be = serve.HipBackend(chain, streams=2, verify=True)
+    budget = serve.footprint(16, 24) * 8
+    be = serve.HipBackend(chain, streams=2, verify=True, budget_bytes=budget)
     trace = workloads.serving_trace(48, rate_per_s=5000.0, seed_stream=9)
     reqs = []
     for i, (t, ln, lvl) in enumerate(trace):
@@ -79,10 +82,11 @@ def test_served_mix_all_levels(gpu):
         reqs.append(serve.Request(i, t, ln, lvl, torch.from_numpy(c.view(np.int64)).cuda(),
                                   torch.from_numpy(d.view(np.int64)).cuda()))
     assert max(r.level for r in reqs) >= 20 and min(r.level for r in reqs) <= 8
-    sched = serve.Scheduler(be, budget_bytes=serve.footprint(16, 24) * 8, streams=2)
+    sched = serve.Scheduler(be, budget_bytes=budget, streams=2)
     sched.run_trace(reqs)
     torch.cuda.synchronize()
     assert all(r.state == "done" for r in reqs), [(r.rid, r.state, r.error) for r in reqs if r.state != "done"]
+    assert 0 < be.peak_held <= budget, (be.peak_held, budget)
     for r in reqs:
         alone = H.ct_tensor(be.view(r.log_n, r.level), r.c, r.d)
         assert torch.equal(alone, r.result), r.rid
