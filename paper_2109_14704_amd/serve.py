@@ -265,6 +265,13 @@ class HipBackend:
         torch, H = self.torch, self.H
         st = self.streams[self.launches % len(self.streams)]
         self.launches += 1
+        # largest group first: its workspace buffer serves the later groups of the step
+        batch = sorted(batch, key=lambda g: -(len(g[1]) * g[0][1] << g[0][0]))
+        if self.ws_cap is not None and batch:
+            (log_n, level), rs = batch[0]
+            need = WORKSPACE_POLYS * len(rs) * level * (1 << log_n) * WORD
+            if H.pool_bytes() + need > self.ws_cap:
+                H.pool_trim()                   # frees idle workspace buffers (waits for their streams)
         st.wait_stream(torch.cuda.current_stream())
         used = []
         with torch.cuda.stream(st):
@@ -295,8 +302,6 @@ class HipBackend:
         for key, slab in handle[1]:
             self.pool.setdefault(key, []).append(slab)
             self.pool.move_to_end(key)
-        if self.ws_cap is not None and self.H.pool_bytes() > self.ws_cap:
-            self.H.pool_trim()                  # frees idle workspace buffers (waits for their streams)
 
 
 def serve_per_request(requests, backend, clock=time.perf_counter):
