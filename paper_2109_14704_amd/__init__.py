@@ -72,6 +72,7 @@ def lib():
             "hentt_last_hip_error": [],
             "hentt_batch_plan_create": [ctypes.POINTER(_Job), _U32, ctypes.c_int, ctypes.POINTER(_VP)],
             "hentt_batch_plan_set_grid": [_VP, _U32],
+            "hentt_batch_plan_set_lookahead": [_VP, _U32],
             "hentt_batch_plan_info": [_VP, ctypes.POINTER(_U32), ctypes.POINTER(_U32), ctypes.POINTER(_U32)],
             "hentt_batch_plan_run": [_VP, _VP],
             "hentt_batch_plan_status": [_VP],
@@ -429,6 +430,11 @@ class BatchPlan:
     def set_grid(self, workgroups):
         self.drop_graph()              # a captured graph holds the old launch shape
         _check(lib().hentt_batch_plan_set_grid(self._h, int(workgroups)), "plan_set_grid")
+
+    def set_lookahead(self, percent):
+        """Pass-2 lookahead in percent of the workgroups serving a queue."""
+        self.drop_graph()
+        _check(lib().hentt_batch_plan_set_lookahead(self._h, int(percent)), "plan_set_lookahead")
 
     def run(self, stream=None):
         _check(lib().hentt_batch_plan_run(self._h, _stream(stream)), "plan_run")

@@ -10,7 +10,7 @@ results equal an oracle-checked result.
 
 Tuned knobs:
   * persistent_grid: the number of persistent workgroups of an uneven-batch
-    plan;
+    plan and the lookahead of its pass-2 tiles;
   * kernel_config: the compiled kernel instance (stage split, words per
     lane, columns per lane) of a transform or fused product at one
     (N, limbs, batch) shape class.
@@ -59,8 +59,9 @@ def _store(d):
     os.replace(tmp, path)
 
 
-def _time(fn, reps=5):
-    fn()
+def _time(fn, reps=10, warm=10):
+    for _ in range(warm):
+        fn()
     torch.cuda.synchronize()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     a.record()
@@ -110,27 +111,37 @@ def _gated_choice(candidates, apply, run, data, check, restore_every_run):
 
 
 def persistent_grid(plan, data, candidates=None, check=None, force=False):
-    """Best workgroup count for `plan` (cached).  data: the plan's device
-    tensors (restored to their contents on return); check(outputs) -> bool:
-    optional verification of the default candidate's outputs."""
+    """Best (workgroup count, pass-2 lookahead %) for `plan` (cached); the
+    plan is left set to it.  data: the
+    plan's device tensors (restored to their contents on return);
+    check(outputs) -> bool: optional verification of the default candidate's
+    outputs.  Returns (workgroups, lookahead percent)."""
     info = plan.info()
     key = "grid/%s/%s/units%d/tiles%d" % (_arch(), source_digest(), info["units"], info["tiles"])
     cache = _load()
     if key in cache and not force:
-        return int(cache[key]["choice"])
+        grid, look = cache[key]["choice"]
+        plan.set_grid(int(grid))
+        plan.set_lookahead(int(look))
+        return int(grid), int(look)
     cus = torch.cuda.get_device_properties(0).multi_processor_count
-    candidates = candidates or [2 * cus, cus, 3 * cus, 4 * cus]
+    candidates = candidates or [(2 * cus, 200), (cus, 200), (3 * cus, 200), (4 * cus, 200), (4 * cus, 100),
+                                (4 * cus, 50), (4 * cus, 400), (2 * cus, 100)]
+
+    def apply(c):
+        plan.set_grid(c[0])
+        plan.set_lookahead(c[1])
 
     def run():
         plan.run()
         plan.status()                      # a tile that gave up waiting fails the candidate loudly
 
-    best, table = _gated_choice(candidates, plan.set_grid, run, data, check, restore_every_run=False)
-    plan.set_grid(best)
+    best, table = _gated_choice(candidates, apply, run, data, check, restore_every_run=False)
+    apply(best)
     cache = _load()
-    cache[key] = {"choice": best, "ms": table}
+    cache[key] = {"choice": list(best), "ms": table}
     _store(cache)
-    return best
+    return tuple(best)
 
 
 def kernel_config(op, tables, run, data, batch_units, check=None, force=False):

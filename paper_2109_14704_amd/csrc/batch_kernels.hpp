@@ -110,7 +110,7 @@ __device__ __forceinline__ uint32_t xcc_id() { return __builtin_amdgcn_s_getreg(
 __device__ __forceinline__ void invalidate_l1() { asm volatile("buffer_inv sc0" ::: "memory"); }
 
 template <bool INV>
-__global__ __launch_bounds__(BATCH_LANES) void k_batch(const BatchUnit *__restrict__ units,
+__global__ __launch_bounds__(BATCH_LANES, 4) void k_batch(const BatchUnit *__restrict__ units,
                                                        const BatchTile *__restrict__ tiles,
                                                        const uint32_t *__restrict__ qoff,
                                                        const uint32_t *__restrict__ qmap, uint32_t *ctl,
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(BATCH_LANES) void k_batch(const BatchUnit *__restri
     const BatchTile tile = tiles[q0 + ti];
     const BatchUnit u = units[tile.unit];
     const uint32_t kind = tile.kind_idx >> 16, idx = tile.kind_idx & 0xffffu;
-    const LimbConst c = *u.lc;
+    const LimbConst c = ld_lc(u.lc);
     if (kind == BT_PASS2) {
       if (tid == 0) {
         uint32_t spins = 0, ok = 1;

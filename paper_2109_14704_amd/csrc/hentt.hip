@@ -159,6 +159,7 @@ struct hentt_batch_plan {
   int dir = 1;
   int device = 0;
   uint32_t nunits = 0, ntiles = 0, grid = 0, nq = 0;
+  uint32_t look_pct = 200;               // pass-2 lookahead, percent of the workgroups serving a queue
   std::vector<BatchUnit> units;          // host copy (queues are rebuilt when the grid changes)
   BatchUnit *d_units = nullptr;
   BatchTile *d_tiles = nullptr;
@@ -210,10 +211,12 @@ uint32_t pass2_tiles(uint32_t ln, int dir) {
 // the units over the queues (largest first, least-loaded queue) and orders
 // each queue.  A queue is two streams merged: pass-1 (and whole) tiles in
 // unit order, and pass-2 tiles in unit order.  A pass-2 tile is placed at
-// least LOOK tiles after the last pass-1 tile of its unit, where LOOK is
-// twice the number of workgroups serving the queue: by the time a workgroup
-// takes the pass-2 tile, the workgroups that took those pass-1 tiles have
-// most likely finished them, so the dependency wait is rarely taken.
+// least LOOK tiles after the last pass-1 tile of its unit, where LOOK is a
+// multiple of the number of workgroups serving the queue (twice by default):
+// by the time a workgroup takes the pass-2 tile, the workgroups that took
+// those pass-1 tiles have most likely finished them, so the dependency wait
+// is rarely taken.  A shorter lookahead keeps a unit's pass-1 results more
+// likely in the XCD's L2 when pass 2 reads them, at the price of more waits.
 int plan_queues(hentt_batch_plan *p) {
   const uint32_t grid = std::max(1u, p->grid);
   uint32_t *d_probe = nullptr;
@@ -288,7 +291,7 @@ int plan_queues(hentt_batch_plan *p) {
   for (uint32_t k = 0; k < BATCH_NQ; ++k) {
     qoff[k] = (uint32_t)tiles.size();
     if (k >= nq) continue;
-    const size_t look = 2 * (size_t)served[k];
+    const size_t look = (size_t)served[k] * p->look_pct / 100;
     const std::vector<uint32_t> &us = qunits[k];
     std::vector<BatchTile> first;  // whole and pass-1 tiles, unit order
     for (uint32_t i : us) {
@@ -727,6 +730,14 @@ int hentt_batch_plan_set_grid(hentt_batch_plan *p, uint32_t workgroups) {
   if (p->graphs.load() > 0) return HENTT_EBUSY;  // captured graphs hold the old launch shape
   if (p->done) HIPCHK(hipEventSynchronize(p->done));
   p->grid = workgroups ? workgroups : (uint32_t)default_grid();
+  return p->nunits ? plan_queues(p) : HENTT_OK;
+}
+
+int hentt_batch_plan_set_lookahead(hentt_batch_plan *p, uint32_t percent) {
+  if (!p || percent > 10000) return HENTT_EINVAL;
+  if (p->graphs.load() > 0) return HENTT_EBUSY;  // captured graphs read the tile list being rewritten
+  if (p->done) HIPCHK(hipEventSynchronize(p->done));
+  p->look_pct = percent;
   return p->nunits ? plan_queues(p) : HENTT_OK;
 }
 

@@ -61,6 +61,23 @@ __device__ __forceinline__ Tw ld_tw(const Tw* t, uint32_t i) {
   return Tw{p[0], p[1]};
 }
 
+// Limb constants through the constant address space as well: with a
+// wave-uniform pointer (also one read from memory) they become scalar loads
+// into SGPRs instead of 24 VGPRs of per-lane copies.
+__device__ __forceinline__ LimbConst ld_lc(const LimbConst *p) {
+  const __attribute__((address_space(4))) uint64_t *w = (const __attribute__((address_space(4))) uint64_t *)p;
+  LimbConst c;
+  c.m = ModQ{w[0], w[1], w[2], w[3], w[4], w[5]};
+  c.ninv = w[6];
+  c.ninv_s = w[7];
+  c.ninvw = w[8];
+  c.ninvw_s = w[9];
+  c.mu = w[10];
+  c.k = (uint32_t)w[11];
+  c.pad = 0;
+  return c;
+}
+
 // ---------------------------------------------------------------- rounds --
 // Forward stages with global index s = LOGN - LO - R + u, u < R.  Stage s
 // pairs j with j + N/2^(s+1) and uses psi_rev[2^s + (j >> (LOGN - s))].

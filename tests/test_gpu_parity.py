@@ -523,15 +523,18 @@ def test_batch_graph_replays_match_eager(gpu):
     plan.close()
 
 
-@pytest.mark.parametrize("grid", [1, 7, 256, 2048])
-def test_batch_grid_sizes(gpu, grid):
-    """Any persistent grid size gives the same words (load balance only)."""
+@pytest.mark.parametrize("grid,look", [(1, 200), (7, 200), (256, 200), (2048, 200), (1024, 0), (1024, 50),
+                                       (512, 1000)])
+def test_batch_grid_sizes(gpu, grid, look):
+    """Any persistent grid size and pass-2 lookahead gives the same words
+    (load balance and waits only)."""
     import torch
-    print("case batch grid %d" % grid, flush=True)
+    print("case batch grid %d lookahead %d" % (grid, look), flush=True)
     H, mods, jobs, tables, xs = _uneven_setup(gpu, 12)
     devs = [dev(x, gpu) for x in xs]
     plan = H.BatchPlan([(d_, tables[ln], L) for d_, (ln, L) in zip(devs, jobs)], +1)
     plan.set_grid(grid)
+    plan.set_lookahead(look)
     plan.run()
     plan.status()
     _check_uneven(xs, devs, jobs, mods, +1)
