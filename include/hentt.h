@@ -279,12 +279,16 @@ int hentt_ntt_batch_status(const hentt_job *jobs, uint32_t njobs, int dir);
 typedef struct hentt_batch_plan hentt_batch_plan;
 int hentt_batch_plan_create(const hentt_job *jobs, uint32_t njobs, int dir, hentt_batch_plan **out);
 int hentt_batch_plan_set_grid(hentt_batch_plan *p, uint32_t workgroups);
-/* set_lookahead: a unit's pass-2 tiles are queued at least `percent` % of
- * the queue's workgroup count after its last pass-1 tile (default 200; at
- * most 10000): smaller values keep pass-1 results likelier in L2, larger
- * values make dependency waits rarer (section III-B tuning constant of the
- * staged transform's schedule).  HENTT_EBUSY while graphs exist. */
-int hentt_batch_plan_set_lookahead(hentt_batch_plan *p, uint32_t percent);
+/* set_schedule: the tile order of each queue (tuning constants of the
+ * staged transform's schedule, section III-B).  Units sharing a twiddle
+ * table are taken in groups of at most group_units (default 8; 1 to 4096)
+ * whose block tiles run block-major across the group, so that tiles reading
+ * the same twiddles run together; a group's pass-2 tiles are queued at least
+ * lookahead_pct % of the queue's workgroup count (default 200; at most
+ * 10000) after its last pass-1 tile: smaller values keep pass-1 results
+ * likelier in L2, larger values make dependency waits rarer.  HENTT_EBUSY
+ * while graphs exist; HENTT_EINVAL out of range. */
+int hentt_batch_plan_set_schedule(hentt_batch_plan *p, uint32_t lookahead_pct, uint32_t group_units);
 int hentt_batch_plan_info(const hentt_batch_plan *p, uint32_t *units, uint32_t *tiles, uint32_t *grid);
 int hentt_batch_plan_run(hentt_batch_plan *p, void *stream);
 int hentt_batch_plan_status(hentt_batch_plan *p);

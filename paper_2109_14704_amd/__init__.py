@@ -72,7 +72,7 @@ def lib():
             "hentt_last_hip_error": [],
             "hentt_batch_plan_create": [ctypes.POINTER(_Job), _U32, ctypes.c_int, ctypes.POINTER(_VP)],
             "hentt_batch_plan_set_grid": [_VP, _U32],
-            "hentt_batch_plan_set_lookahead": [_VP, _U32],
+            "hentt_batch_plan_set_schedule": [_VP, _U32, _U32],
             "hentt_batch_plan_info": [_VP, ctypes.POINTER(_U32), ctypes.POINTER(_U32), ctypes.POINTER(_U32)],
             "hentt_batch_plan_run": [_VP, _VP],
             "hentt_batch_plan_status": [_VP],
@@ -431,10 +431,11 @@ class BatchPlan:
         self.drop_graph()              # a captured graph holds the old launch shape
         _check(lib().hentt_batch_plan_set_grid(self._h, int(workgroups)), "plan_set_grid")
 
-    def set_lookahead(self, percent):
-        """Pass-2 lookahead in percent of the workgroups serving a queue."""
+    def set_schedule(self, lookahead_pct=200, group_units=8):
+        """Tile order: pass-2 lookahead in percent of the workgroups serving a
+        queue, and the units of one twiddle table ordered block-major together."""
         self.drop_graph()
-        _check(lib().hentt_batch_plan_set_lookahead(self._h, int(percent)), "plan_set_lookahead")
+        _check(lib().hentt_batch_plan_set_schedule(self._h, int(lookahead_pct), int(group_units)), "plan_set_schedule")
 
     def run(self, stream=None):
         _check(lib().hentt_batch_plan_run(self._h, _stream(stream)), "plan_run")

@@ -111,26 +111,27 @@ def _gated_choice(candidates, apply, run, data, check, restore_every_run):
 
 
 def persistent_grid(plan, data, candidates=None, check=None, force=False):
-    """Best (workgroup count, pass-2 lookahead %) for `plan` (cached); the
-    plan is left set to it.  data: the
+    """Best (workgroup count, pass-2 lookahead %, group units) for `plan`
+    (cached); the plan is left set to it.  data: the
     plan's device tensors (restored to their contents on return);
     check(outputs) -> bool: optional verification of the default candidate's
-    outputs.  Returns (workgroups, lookahead percent)."""
+    outputs.  Returns (workgroups, lookahead percent, group units)."""
     info = plan.info()
     key = "grid/%s/%s/units%d/tiles%d" % (_arch(), source_digest(), info["units"], info["tiles"])
     cache = _load()
     if key in cache and not force:
-        grid, look = cache[key]["choice"]
+        grid, look, group = cache[key]["choice"]
         plan.set_grid(int(grid))
-        plan.set_lookahead(int(look))
-        return int(grid), int(look)
+        plan.set_schedule(int(look), int(group))
+        return int(grid), int(look), int(group)
     cus = torch.cuda.get_device_properties(0).multi_processor_count
-    candidates = candidates or [(2 * cus, 200), (cus, 200), (3 * cus, 200), (4 * cus, 200), (4 * cus, 100),
-                                (4 * cus, 50), (4 * cus, 400), (2 * cus, 100)]
+    candidates = candidates or [(2 * cus, 200, 8), (4 * cus, 200, 8), (3 * cus, 200, 8), (4 * cus, 100, 8),
+                                (4 * cus, 50, 8), (4 * cus, 200, 1), (4 * cus, 200, 4), (4 * cus, 200, 16),
+                                (4 * cus, 200, 64), (4 * cus, 400, 8)]
 
     def apply(c):
         plan.set_grid(c[0])
-        plan.set_lookahead(c[1])
+        plan.set_schedule(c[1], c[2])
 
     def run():
         plan.run()

@@ -160,6 +160,7 @@ struct hentt_batch_plan {
   int device = 0;
   uint32_t nunits = 0, ntiles = 0, grid = 0, nq = 0;
   uint32_t look_pct = 200;               // pass-2 lookahead, percent of the workgroups serving a queue
+  uint32_t group_max = 8;                // units of one twiddle table ordered block-major together
   std::vector<BatchUnit> units;          // host copy (queues are rebuilt when the grid changes)
   BatchUnit *d_units = nullptr;
   BatchTile *d_tiles = nullptr;
@@ -209,9 +210,9 @@ uint32_t pass2_tiles(uint32_t ln, int dir) {
 
 // Places the plan's workgroups (probe kernel), maps XCDs to queues, spreads
 // the units over the queues (largest first, least-loaded queue) and orders
-// each queue.  A queue is two streams merged: pass-1 (and whole) tiles in
-// unit order, and pass-2 tiles in unit order.  A pass-2 tile is placed at
-// least LOOK tiles after the last pass-1 tile of its unit, where LOOK is a
+// each queue.  A queue is two streams merged: pass-1 (and whole) tiles, and
+// pass-2 tiles, each grouped by twiddle table.  A group's pass-2 tiles are placed at
+// least LOOK tiles after the group's last pass-1 tile, where LOOK is a
 // multiple of the number of workgroups serving the queue (twice by default):
 // by the time a workgroup takes the pass-2 tile, the workgroups that took
 // those pass-1 tiles have most likely finished them, so the dependency wait
@@ -293,25 +294,61 @@ int plan_queues(hentt_batch_plan *p) {
     if (k >= nq) continue;
     const size_t look = (size_t)served[k] * p->look_pct / 100;
     const std::vector<uint32_t> &us = qunits[k];
-    std::vector<BatchTile> first;  // whole and pass-1 tiles, unit order
+    // groups: runs of at most group_max consecutive units sharing a twiddle
+    // table (short runs keep column tiles, which are HBM-bound, interleaved
+    // with block tiles, which are ALU-bound)
+    std::vector<std::vector<uint32_t>> groups;
     for (uint32_t i : us) {
-      const BatchUnit &u = p->units[i];
-      if (u.logn == BATCH_B) first.push_back({i, (uint32_t)BT_WHOLE << 16});
-      for (uint32_t t = 0; t < u.pass1; ++t) first.push_back({i, ((uint32_t)BT_PASS1 << 16) | t});
+      if (groups.empty() || p->units[groups.back()[0]].tw != p->units[i].tw || groups.back().size() >= p->group_max)
+        groups.emplace_back();
+      groups.back().push_back(i);
+    }
+    // Block passes read about as many twiddle bytes per block as data bytes,
+    // and block b of every unit of a group reads the same twiddles: their
+    // tiles go block-major across the group's units, so that consecutive
+    // tiles (run at about the same time) share the twiddles in L2.  Column
+    // passes read a few scalar twiddles per column: unit-major.
+    const bool p1_blocks = p->dir < 0;  // inverse: pass 1 = blocks, pass 2 = columns
+    std::vector<BatchTile> first;       // whole and pass-1 tiles
+    std::vector<uint32_t> first_group;
+    std::vector<size_t> gleft(groups.size(), 0), gready(groups.size(), 0);
+    for (uint32_t gi = 0; gi < groups.size(); ++gi) {
+      const std::vector<uint32_t> &g = groups[gi];
+      const BatchUnit &u0 = p->units[g[0]];
+      if (u0.logn == BATCH_B) {
+        for (uint32_t i : g) first.push_back({i, (uint32_t)BT_WHOLE << 16}), first_group.push_back(gi);
+        continue;
+      }
+      const uint32_t n1 = u0.pass1;
+      gleft[gi] = (size_t)n1 * g.size();
+      if (p1_blocks) {
+        for (uint32_t t = 0; t < n1; ++t)
+          for (uint32_t i : g) first.push_back({i, ((uint32_t)BT_PASS1 << 16) | t}), first_group.push_back(gi);
+      } else {
+        for (uint32_t i : g)
+          for (uint32_t t = 0; t < n1; ++t) first.push_back({i, ((uint32_t)BT_PASS1 << 16) | t}), first_group.push_back(gi);
+      }
     }
     size_t next = 0;
     auto emit_first = [&]() {
-      const BatchTile bt = first[next++];
+      const BatchTile bt = first[next];
+      const uint32_t gi = first_group[next++];
       tiles.push_back(bt);
-      if ((bt.kind_idx >> 16) == BT_PASS1 && (bt.kind_idx & 0xffffu) + 1 == p->units[bt.unit].pass1)
-        ready[bt.unit] = tiles.size();
+      if ((bt.kind_idx >> 16) == BT_PASS1 && --gleft[gi] == 0) gready[gi] = tiles.size();
     };
-    for (uint32_t i : us) {
-      const uint32_t n2 = pass2_tiles(p->units[i].logn, p->dir);
+    for (uint32_t gi = 0; gi < groups.size(); ++gi) {
+      const std::vector<uint32_t> &g = groups[gi];
+      const uint32_t n2 = pass2_tiles(p->units[g[0]].logn, p->dir);
       if (n2 == 0) continue;
-      // every pass-1 tile of unit i is queued, and LOOK more tiles after it
-      while (next < first.size() && (ready[i] == 0 || tiles.size() < ready[i] + look)) emit_first();
-      for (uint32_t t = 0; t < n2; ++t) tiles.push_back({i, ((uint32_t)BT_PASS2 << 16) | t});
+      // every pass-1 tile of the group is queued, and LOOK more tiles after it
+      while (next < first.size() && (gready[gi] == 0 || tiles.size() < gready[gi] + look)) emit_first();
+      if (!p1_blocks) {
+        for (uint32_t t = 0; t < n2; ++t)
+          for (uint32_t i : g) tiles.push_back({i, ((uint32_t)BT_PASS2 << 16) | t});
+      } else {
+        for (uint32_t i : g)
+          for (uint32_t t = 0; t < n2; ++t) tiles.push_back({i, ((uint32_t)BT_PASS2 << 16) | t});
+      }
     }
     while (next < first.size()) emit_first();
   }
@@ -733,11 +770,12 @@ int hentt_batch_plan_set_grid(hentt_batch_plan *p, uint32_t workgroups) {
   return p->nunits ? plan_queues(p) : HENTT_OK;
 }
 
-int hentt_batch_plan_set_lookahead(hentt_batch_plan *p, uint32_t percent) {
-  if (!p || percent > 10000) return HENTT_EINVAL;
+int hentt_batch_plan_set_schedule(hentt_batch_plan *p, uint32_t lookahead_pct, uint32_t group_units) {
+  if (!p || lookahead_pct > 10000 || group_units == 0 || group_units > 4096) return HENTT_EINVAL;
   if (p->graphs.load() > 0) return HENTT_EBUSY;  // captured graphs read the tile list being rewritten
   if (p->done) HIPCHK(hipEventSynchronize(p->done));
-  p->look_pct = percent;
+  p->look_pct = lookahead_pct;
+  p->group_max = group_units;
   return p->nunits ? plan_queues(p) : HENTT_OK;
 }
 

@@ -523,18 +523,18 @@ def test_batch_graph_replays_match_eager(gpu):
     plan.close()
 
 
-@pytest.mark.parametrize("grid,look", [(1, 200), (7, 200), (256, 200), (2048, 200), (1024, 0), (1024, 50),
-                                       (512, 1000)])
-def test_batch_grid_sizes(gpu, grid, look):
+@pytest.mark.parametrize("grid,look,group", [(1, 200, 8), (7, 200, 8), (256, 200, 8), (2048, 200, 8), (1024, 0, 8),
+                                             (1024, 50, 1), (512, 1000, 4096), (1024, 200, 3)])
+def test_batch_grid_sizes(gpu, grid, look, group):
     """Any persistent grid size and pass-2 lookahead gives the same words
     (load balance and waits only)."""
     import torch
-    print("case batch grid %d lookahead %d" % (grid, look), flush=True)
+    print("case batch grid %d lookahead %d group %d" % (grid, look, group), flush=True)
     H, mods, jobs, tables, xs = _uneven_setup(gpu, 12)
     devs = [dev(x, gpu) for x in xs]
     plan = H.BatchPlan([(d_, tables[ln], L) for d_, (ln, L) in zip(devs, jobs)], +1)
     plan.set_grid(grid)
-    plan.set_lookahead(look)
+    plan.set_schedule(look, group)
     plan.run()
     plan.status()
     _check_uneven(xs, devs, jobs, mods, +1)

@@ -82,15 +82,16 @@ def test_uneven_512_jobs_tuned_graph_replay(gpu, full_uneven, tmp_path, monkeypa
     spec = [(d_, tables[ln], L) for d_, (ln, L) in zip(devs, jobs)]
     plan_f, plan_i = H.BatchPlan(spec, +1), H.BatchPlan(spec, -1)
     print("case uneven 512 jobs: autotuning the persistent grid", flush=True)
-    grid, look = autotune.persistent_grid(plan_f, devs, check=lambda outs: _equal_all(outs, fw) is None)
+    grid, look, group = autotune.persistent_grid(plan_f, devs, check=lambda outs: _equal_all(outs, fw) is None)
     assert grid > 0 and plan_f.info()["grid"] == grid
     plan_i.set_grid(grid)
-    plan_i.set_lookahead(look)
+    plan_i.set_schedule(look, group)
     assert _equal_all(devs, xs) is None          # the tuner restored the inputs
     plan_f.capture()
     plan_i.capture()
     for rep in range(2):
-        print("case uneven 512 jobs: graph replay %d at grid %d, lookahead %d%%" % (rep, grid, look), flush=True)
+        print("case uneven 512 jobs: graph replay %d at grid %d, lookahead %d%%, groups of %d" % (rep, grid, look, group),
+              flush=True)
         plan_f.replay()
         plan_f.status()
         assert _equal_all(devs, fw) is None, rep
