@@ -16,7 +16,7 @@
 
 #include "modarith.hpp"
 
-namespace {
+namespace hentt_mb {
 
 typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
 
@@ -107,7 +107,9 @@ __global__ __launch_bounds__(256) void mb_issue_k(uint64_t *out, uint32_t iters,
   }
 }
 
-}  // namespace
+}  // namespace hentt_mb
+
+using namespace hentt_mb;
 
 extern "C" {
 
