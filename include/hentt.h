@@ -237,6 +237,36 @@ int hentt_ct_tensor(const hentt_tables *t, const uint64_t *c, const uint64_t *d,
 int hentt_ct_tensor_noalloc(const hentt_tables *t, const uint64_t *c, const uint64_t *d, uint64_t *out,
                             uint32_t batch, uint32_t flags, void *stream);
 
+/* One ciphertext tensor product of a grouped call: c, d [batch][2][limbs][N]
+ * -> out [batch][3][limbs][N] with the moduli of t (a table or a level
+ * view: limbs = its limb count, N = its ring dimension).  reserved: 0. */
+typedef struct {
+  const uint64_t *c;
+  const uint64_t *d;
+  uint64_t *out;
+  const hentt_tables *t;
+  uint32_t batch;
+  uint32_t reserved;
+} hentt_ct_job;
+
+/* Many ciphertext tensor products (section II-A, Mul) of mixed levels and
+ * ring dimensions in a few launches: the products of every job of one N run
+ * in one launch per kernel of the product (forward column pass, fused block
+ * kernel, inverse column pass), jobs of larger N first, at most 24 jobs per
+ * launch sequence (more jobs: further sequences).  This is continuous
+ * batching's device side: a step of many small requests fills the GPU
+ * without gathering their operands into one buffer.  Each job's result
+ * equals hentt_ct_tensor on the same job; flags as there and common to all
+ * jobs.  jobs is a HOST array read before the call returns; the data are
+ * DEVICE pointers owned by the caller.  HENTT_EINVAL: jobs NULL with
+ * njobs > 0, a NULL pointer, batch 0, reserved != 0, batch x limbs >= 2^24,
+ * or an output range that overlaps another job's output or any job's input.
+ * njobs = 0 enqueues nothing.  With coefficient-domain inputs and N > 2^12
+ * the forward column pass writes a workspace of 4 batch limbs N words per
+ * job (one buffer of the largest launch sequence's total, from the pool).
+ * The stage split at each N is the single-job product's default one. */
+int hentt_ct_tensor_grouped(const hentt_ct_job *jobs, uint32_t njobs, uint32_t flags, void *stream);
+
 /* One polynomial set of an uneven batch: data [batch][limbs][N] in place,
  * transformed with the first `limbs` moduli of `t` (limbs <= t's limbs). */
 typedef struct {

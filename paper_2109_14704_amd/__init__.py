@@ -14,7 +14,7 @@ import torch
 __all__ = ["HenttError", "Tables", "ntt_fwd", "ntt_inv", "dyadic_mul", "polymul", "ct_tensor", "ntt_batch",
            "psi", "lib", "LIB_PATH", "prof_enable", "prof_read", "BatchPlan", "stage_split", "ntt_fwd_variant",
            "rescale", "ct_matmul", "relin", "check_canonical", "ntt_batch_status", "pool_bytes", "pool_trim",
-           "NonCanonicalError", "tune_count", "tune_describe", "shape_class", "tune_select", "tune_get", "TUNE_OPS"]
+           "NonCanonicalError", "ct_tensor_grouped", "tune_count", "tune_describe", "shape_class", "tune_select", "tune_get", "TUNE_OPS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("HENTT_LIB") or os.path.join(_HERE, "libhentt.so")  # HENTT_LIB: alternative build
@@ -36,6 +36,10 @@ class NonCanonicalError(HenttError):
 
 class _Job(ctypes.Structure):
     _fields_ = [("data", _VP), ("t", _VP), ("limbs", _U32), ("batch", _U32)]
+
+
+class _CtJob(ctypes.Structure):
+    _fields_ = [("c", _VP), ("d", _VP), ("out", _VP), ("t", _VP), ("batch", _U32), ("reserved", _U32)]
 
 
 _lib = None
@@ -64,6 +68,7 @@ def lib():
             "hentt_dyadic_mul": [_VP, _VP, _VP, _VP, _U32, _VP],
             "hentt_polymul": [_VP, _VP, _VP, _VP, _U32, _VP],
             "hentt_ct_tensor": [_VP, _VP, _VP, _VP, _U32, _U32, _VP],
+            "hentt_ct_tensor_grouped": [ctypes.POINTER(_CtJob), _U32, _U32, _VP],
             "hentt_ntt_batch": [ctypes.POINTER(_Job), _U32, ctypes.c_int, _VP],
             "hentt_ntt_batch_status": [ctypes.POINTER(_Job), _U32, ctypes.c_int],
             "hentt_check_canonical": [_VP, _VP, _U32, ctypes.POINTER(_U64), ctypes.POINTER(_U64), _VP],
@@ -395,6 +400,27 @@ def ct_tensor(tables, c, d, out=None, in_ntt=False, out_ntt=False, stream=None):
     _check(lib().hentt_ct_tensor(tables.handle, _words(c, "c"), _words(d, "d"), _words(out, "out"), batch, flags,
                                  _stream(stream)), "hentt_ct_tensor")
     return out
+
+
+def ct_tensor_grouped(jobs, in_ntt=False, out_ntt=False, stream=None):
+    """Many ciphertext tensors in a few launches (hentt_ct_tensor_grouped).
+    jobs: (tables, c, d, out) with c, d [batch, 2, limbs, N] and out
+    [batch, 3, limbs, N] at the tables' (or level view's) limbs and N; the
+    outputs are written in place."""
+    arr = (_CtJob * len(jobs))()
+    for i, (t, c, d, out) in enumerate(jobs):
+        if c.shape != d.shape or c.dim() != 4 or c.shape[1] != 2:
+            raise HenttError("job %d: c and d must both have shape [batch, 2, limbs, N]" % i)
+        batch = _batch_of(t, c, per_item=2, name="c")
+        if tuple(out.shape) != (batch, 3, t.limbs, t.n):
+            raise HenttError("job %d: out must have shape [batch, 3, limbs, N]" % i)
+        arr[i].c = _words(c, "c")
+        arr[i].d = _words(d, "d")
+        arr[i].out = _words(out, "out")
+        arr[i].t = t.handle
+        arr[i].batch = batch
+    flags = (HENTT_IN_NTT if in_ntt else 0) | (HENTT_OUT_NTT if out_ntt else 0)
+    _check(lib().hentt_ct_tensor_grouped(arr, len(jobs), flags, _stream(stream)), "hentt_ct_tensor_grouped")
 
 
 def _job_array(jobs):

@@ -421,14 +421,17 @@ __device__ __forceinline__ void col_pass2(const uint64_t *src, uint64_t *dst, ui
   }
 }
 
+// Workgroup `blk` of a column pass over batch x limbs units of every
+// component of `a` (the body of k_cols and of its grouped form).
 template <int LOGN, int E, bool INV>
-__global__ __launch_bounds__(256) void k_cols(ColArgs a, const Tw *__restrict__ tw, const LimbConst *__restrict__ lc,
-                                              uint32_t batch, uint32_t limbs) {
+__device__ __forceinline__ void cols_block(const ColArgs &a, const Tw *__restrict__ tw,
+                                           const LimbConst *__restrict__ lc, uint32_t batch, uint32_t limbs,
+                                           uint32_t blk) {
   constexpr uint32_t CPL = ColCpl<E>::value;
   constexpr uint32_t tiles = (1u << (LOGN - E)) / (256 * CPL);
   const uint32_t units = batch * limbs;
-  const uint32_t tile = blockIdx.x % tiles;
-  const uint32_t r = blockIdx.x / tiles;
+  const uint32_t tile = blk % tiles;
+  const uint32_t r = blk / tiles;
   const uint32_t comp = r / units, u = r % units;
   const uint32_t limb = u / batch, b = u % batch;
   const LimbConst c = lc[limb];
@@ -438,6 +441,17 @@ __global__ __launch_bounds__(256) void k_cols(ColArgs a, const Tw *__restrict__ 
   const Tw *t = tw + ((size_t)limb * 2 + (INV ? 1 : 0)) * (1u << LOGN);
   if constexpr (CPL == 2) col_pass2<LOGN, E, INV>(src, dst, tile * 512 + 2 * threadIdx.x, t, c);
   else col_pass<LOGN, E, INV>(src, dst, tile * 256 + threadIdx.x, t, c);
+}
+
+// Workgroups per component of a column pass over `units` (batch x limbs) units.
+template <int LOGN, int E> constexpr uint32_t cols_blocks_per_unit() {
+  return (1u << (LOGN - E)) / (256 * ColCpl<E>::value);
+}
+
+template <int LOGN, int E, bool INV>
+__global__ __launch_bounds__(256) void k_cols(ColArgs a, const Tw *__restrict__ tw, const LimbConst *__restrict__ lc,
+                                              uint32_t batch, uint32_t limbs) {
+  cols_block<LOGN, E, INV>(a, tw, lc, batch, limbs, blockIdx.x);
 }
 
 // Block pass of the forward transform: stages LOGN-B .. LOGN-1 on contiguous
@@ -573,16 +587,17 @@ template <int MODE, int E> __device__ __forceinline__ void reduce_for_mont(uint6
 // and lc must hold the folded constants (N^-1 R in place of N^-1), also for
 // the inverse column pass that completes the transform.  Without DO_INV the
 // products are exact (Barrett) and lc the plain constants.
+// Workgroup `blk` of the fused product over batch x limbs units (the body of
+// k_prod and of its grouped form).
 template <int LOGN, int B, int E, int MODE, bool DO_FWD, bool DO_INV>
-__global__ __launch_bounds__(1 << (B - E)) void k_prod(ProdArgs a, const Tw *__restrict__ tw,
-                                                        const LimbConst *__restrict__ lc,
-                                                        const MontLimb *__restrict__ mont, uint32_t batch,
-                                                        uint32_t limbs) {
+__device__ __forceinline__ void prod_block(const ProdArgs &a, const Tw *__restrict__ tw,
+                                           const LimbConst *__restrict__ lc, const MontLimb *__restrict__ mont,
+                                           uint32_t batch, uint32_t limbs, uint32_t blk) {
   constexpr int NIN = ProdShape<MODE>::NIN, NOUT = ProdShape<MODE>::NOUT;
   __shared__ uint64_t lds[(DO_FWD || DO_INV) ? LdsSize<B>::value : 2];
   constexpr uint32_t tiles = 1u << (LOGN - B);
-  const uint32_t tile = blockIdx.x % tiles;
-  const uint32_t r = blockIdx.x / tiles;
+  const uint32_t tile = blk % tiles;
+  const uint32_t r = blk / tiles;
   const uint32_t limb = r / batch, b = r % batch;
   const LimbConst c = lc[limb];
   const Tw *t = tw + (size_t)limb * 2 * (1u << LOGN);
@@ -645,6 +660,14 @@ __global__ __launch_bounds__(1 << (B - E)) void k_prod(ProdArgs a, const Tw *__r
       store_global_m0<B, E>(v, a.out[o] + out_off, lds, tid);
     }
   }
+}
+
+template <int LOGN, int B, int E, int MODE, bool DO_FWD, bool DO_INV>
+__global__ __launch_bounds__(1 << (B - E)) void k_prod(ProdArgs a, const Tw *__restrict__ tw,
+                                                        const LimbConst *__restrict__ lc,
+                                                        const MontLimb *__restrict__ mont, uint32_t batch,
+                                                        uint32_t limbs) {
+  prod_block<LOGN, B, E, MODE, DO_FWD, DO_INV>(a, tw, lc, mont, batch, limbs, blockIdx.x);
 }
 
 // Encrypted element-wise polynomial matrix product (section IV-E), NTT
@@ -744,11 +767,11 @@ __global__ __launch_bounds__(256) void k_ct_matmul(const uint64_t *__restrict__ 
 // words of one (batch entry, limb), coalesced, limb constants uniform per
 // workgroup.
 template <int MODE>
-__global__ __launch_bounds__(256) void k_elem(ProdArgs a, const LimbConst *__restrict__ lc, uint32_t batch,
-                                              uint32_t limbs, uint32_t log_n, uint32_t tiles) {
+__device__ __forceinline__ void elem_block(const ProdArgs &a, const LimbConst *__restrict__ lc, uint32_t batch,
+                                           uint32_t limbs, uint32_t log_n, uint32_t tiles, uint32_t blk) {
   constexpr int NIN = ProdShape<MODE>::NIN, NOUT = ProdShape<MODE>::NOUT;
-  const uint32_t tile = blockIdx.x % tiles;
-  const uint32_t r = blockIdx.x / tiles;
+  const uint32_t tile = blk % tiles;
+  const uint32_t r = blk / tiles;
   const uint32_t limb = r / batch, b = r % batch;
   const LimbConst c = lc[limb];
   const uint32_t n = 1u << log_n;
@@ -770,6 +793,12 @@ __global__ __launch_bounds__(256) void k_elem(ProdArgs a, const LimbConst *__res
       for (int o = 0; o < NOUT; ++o) a.out[o][out_off + i] = Y[o][s];
     }
   }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_elem(ProdArgs a, const LimbConst *__restrict__ lc, uint32_t batch,
+                                              uint32_t limbs, uint32_t log_n, uint32_t tiles) {
+  elem_block<MODE>(a, lc, batch, limbs, log_n, tiles, blockIdx.x);
 }
 
 }  // namespace hentt

@@ -2,22 +2,24 @@
 section II-A) over requests of mixed N and level.
 
 Requests arrive over time (Poisson traces in the benchmark).  The scheduler
-admits a request when its HBM footprint fits the budget, groups the
-admitted requests of equal (N, level) into one batched call, and keeps up to
-`streams` steps in flight on separate streams, so requests that arrive while
-earlier ones run join the next step as soon as a stream and memory free up.
+admits a request when its HBM footprint fits the budget, launches everything
+admitted as one step, and keeps up to `streams` steps in flight on separate
+streams, so requests that arrive while earlier ones run join the next step
+as soon as a stream and memory free up.  On the GPU a step is one grouped
+call (hentt_ct_tensor_grouped): one job per request, reading the request's
+device-resident operands in place, all requests of one N in the same three
+launches whatever their levels.
 
 The footprint is what a request makes the device hold while it is in
 flight: 88 L N bytes for L limbs of N words -- its two input ciphertexts (4
-polynomials) and the 3-polynomial tensor output in the step's slab, plus the
-4 polynomials of the library's forward-column-pass workspace.  The GPU
-backend keeps what it holds within the budget: slabs are sized exactly to
-their step and pooled for reuse (the memory cache of section III-C-1), idle
-slabs are freed before a new one would take the slab total past its share
-of the budget, and the library's workspace pool is trimmed when it holds
-more than its share.  Latency = completion of the request's step minus its
-arrival; completion is observed with stream events, the only host
-synchronisation.
+polynomials, resident from its arrival), its 3-polynomial tensor output and
+the 4 polynomials of the library's forward-column-pass workspace.  The GPU
+backend keeps what it holds within the budget: output buffers are pooled
+for reuse (the memory cache of section III-C-1) and idle ones are freed
+before a new one would take their total past the output share of the
+budget, and the library's workspace pool is trimmed when it would exceed
+its share.  Latency = completion of the request's step minus its arrival;
+completion is observed with stream events, the only host synchronisation.
 
 The scheduling logic is backend-independent: HipBackend runs on the GPU
 through the library's C ABI; the unit tests drive the same scheduler with a
@@ -31,13 +33,14 @@ import numpy as np
 WORD = 8
 
 
-SLAB_POLYS = 7       # c, d (2 polynomials each) and the tensor output (3)
+INPUT_POLYS = 4      # c, d (2 polynomials each), the request's own device buffers
+OUTPUT_POLYS = 3     # the tensor output, from the backend's pool
 WORKSPACE_POLYS = 4  # the library's forward column pass over c0, c1, d0, d1
 
 
 def footprint(log_n, level):
     """HBM bytes a request makes the device hold while it is admitted."""
-    return (SLAB_POLYS + WORKSPACE_POLYS) * level * (1 << log_n) * WORD
+    return (INPUT_POLYS + OUTPUT_POLYS + WORKSPACE_POLYS) * level * (1 << log_n) * WORD
 
 
 class Request:
@@ -55,13 +58,18 @@ class Request:
 
 
 class Scheduler:
-    """Admission by footprint + continuous batching over `streams` in-flight steps."""
+    """Admission by footprint + continuous batching over `streams` in-flight steps.
 
-    def __init__(self, backend, budget_bytes, streams=2, max_group=64, clock=time.perf_counter):
+    A step takes the admitted requests in arrival order up to step_bytes of
+    footprint (default: budget / streams), so that under a full queue the
+    next step is already launched while the current one runs."""
+
+    def __init__(self, backend, budget_bytes, streams=2, max_group=64, clock=time.perf_counter, step_bytes=None):
         self.be = backend
         self.budget = budget_bytes
         self.reserved = 0
         self.streams = streams
+        self.step_bytes = step_bytes if step_bytes is not None else budget_bytes // max(1, streams)
         self.max_group = max_group
         self.clock = clock
         self.waiting = collections.deque()      # arrived, not yet admitted (FIFO)
@@ -134,16 +142,24 @@ class Scheduler:
         self.inflight = still
 
     def _launch(self):
+        """Launch one step from the admitted requests; False if none was launched."""
         if not self.admitted or len(self.inflight) >= self.streams:
-            return
-        groups = collections.OrderedDict()
+            return False
+        take, size = 0, 0
         for r in self.admitted:
+            fp = footprint(r.log_n, r.level)
+            if take and size + fp > self.step_bytes:
+                break
+            take += 1
+            size += fp
+        step, self.admitted = self.admitted[:take], self.admitted[take:]
+        groups = collections.OrderedDict()
+        for r in step:
             groups.setdefault((r.log_n, r.level), []).append(r)
         batch = []
         for key, rs in groups.items():
             for i in range(0, len(rs), self.max_group):
                 batch.append((key, rs[i:i + self.max_group]))
-        self.admitted = []
         now = self.clock()
         try:
             handle = self.be.launch(batch, slot=len(self.inflight))
@@ -155,18 +171,20 @@ class Scheduler:
                     r.t_done = self.clock()
                     self._release(r)
                     self.done.append(r)
-            return
+            return True
         reqs = [r for _, rs in batch for r in rs]
         for r in reqs:
             r.state = "launched"
             r.t_launch = now
         self.inflight.append((handle, reqs))
         self.steps += 1
+        return True
 
     def tick(self):
         self._poll()
         self._admit()
-        self._launch()
+        while self._launch():
+            pass
 
     def idle(self):
         return not (self.waiting or self.admitted or self.inflight)
@@ -201,13 +219,15 @@ def latency_stats(reqs):
 
 # ============================================================ GPU backend
 class HipBackend:
-    """Steps on the GPU: each (N, level) group is gathered into a slab
-    (device-to-device copies stand in for the upload of the ciphertexts) and
-    multiplied by one hentt_ct_tensor call; one stream per in-flight step.
+    """Steps on the GPU: one hentt_ct_tensor_grouped call per step with one
+    job per request (operands read in place, output into a pooled buffer);
+    one stream per in-flight step.
 
-    budget_bytes bounds what the backend holds: slabs up to the slab share
-    (7/11) of it, the library's workspace pool up to the workspace share
-    (4/11).  held_bytes() reports both; peak_held the largest value seen."""
+    budget_bytes bounds what the backend holds: output buffers up to the
+    output share (3/11) of it, the library's workspace pool up to the
+    workspace share (4/11); the request operands (4/11) are the client's.
+    held_bytes() reports outputs + workspace; peak_held the largest value
+    seen."""
 
     def __init__(self, chain, log_ns=(14, 15, 16), streams=2, verify=False, budget_bytes=None):
         import torch
@@ -216,13 +236,13 @@ class HipBackend:
         self.tables = {ln: H.Tables(ln, chain) for ln in log_ns}
         self.views = {}
         self.streams = [torch.cuda.Stream() for _ in range(streams)]
-        self.pool = collections.OrderedDict()   # (log_n, level, count) -> free slabs [c, d, out], oldest first
+        self.pool = collections.OrderedDict()   # (log_n, level) -> free output buffers, oldest first
         self.keep_results = verify
         self.launches = 0
-        share = SLAB_POLYS + WORKSPACE_POLYS
-        self.slab_cap = None if budget_bytes is None else budget_bytes * SLAB_POLYS // share
+        share = INPUT_POLYS + OUTPUT_POLYS + WORKSPACE_POLYS
+        self.out_cap = None if budget_bytes is None else budget_bytes * OUTPUT_POLYS // share
         self.ws_cap = None if budget_bytes is None else budget_bytes * WORKSPACE_POLYS // share
-        self.slab_bytes = 0                      # every slab allocated and not freed, busy or idle
+        self.out_bytes = 0                       # every output buffer allocated and not freed, busy or idle
         self.peak_held = 0
 
     def view(self, log_n, level):
@@ -232,60 +252,61 @@ class HipBackend:
         return self.views[key]
 
     def held_bytes(self):
-        return self.slab_bytes + self.H.pool_bytes()
+        return self.out_bytes + self.H.pool_bytes()
 
     def _free_idle(self, need):
-        """Free idle slabs, oldest first, until `need` more bytes fit the slab share."""
-        while self.slab_cap is not None and self.slab_bytes + need > self.slab_cap:
+        """Free idle output buffers, oldest first, until `need` more bytes fit the output share."""
+        while self.out_cap is not None and self.out_bytes + need > self.out_cap:
             key = next((k for k, v in self.pool.items() if v), None)
             if key is None:
                 break
-            slab = self.pool[key].pop(0)
-            self.slab_bytes -= sum(t.numel() * WORD for t in slab)
+            buf = self.pool[key].pop(0)
+            self.out_bytes -= buf.numel() * WORD
             if not self.pool[key]:
                 del self.pool[key]
 
-    def _slab(self, log_n, level, count):
-        free = self.pool.get((log_n, level, count))
+    def _out(self, log_n, level):
+        free = self.pool.get((log_n, level))
         if free:
-            slab = free.pop(0)
+            buf = free.pop(0)
             if not free:
-                del self.pool[(log_n, level, count)]
-            return slab
-        torch = self.torch
-        n = 1 << log_n
-        need = SLAB_POLYS * count * level * n * WORD
+                del self.pool[(log_n, level)]
+            return buf
+        need = OUTPUT_POLYS * level * (1 << log_n) * WORD
         self._free_idle(need)
-        mk = lambda k: torch.empty((count, k, level, n), dtype=torch.int64, device="cuda:0")
-        slab = [mk(2), mk(2), mk(3)]
-        self.slab_bytes += need
-        return slab
+        buf = self.torch.empty((1, OUTPUT_POLYS, level, 1 << log_n), dtype=self.torch.int64, device="cuda:0")
+        self.out_bytes += need
+        return buf
+
+    def _put(self, key, buf):
+        self.pool.setdefault(key, []).append(buf)
+        self.pool.move_to_end(key)
 
     def launch(self, batch, slot=0):
         torch, H = self.torch, self.H
         st = self.streams[self.launches % len(self.streams)]
         self.launches += 1
-        # largest group first: its workspace buffer serves the later groups of the step
-        batch = sorted(batch, key=lambda g: -(len(g[1]) * g[0][1] << g[0][0]))
-        if self.ws_cap is not None and batch:
-            (log_n, level), rs = batch[0]
-            need = WORKSPACE_POLYS * len(rs) * level * (1 << log_n) * WORD
+        reqs = [r for _, rs in batch for r in rs]
+        if self.ws_cap is not None:
+            # at most every job's workspace in one launch sequence
+            need = sum(WORKSPACE_POLYS * r.level * (1 << r.log_n) * WORD for r in reqs)
             if H.pool_bytes() + need > self.ws_cap:
                 H.pool_trim()                   # frees idle workspace buffers (waits for their streams)
-        st.wait_stream(torch.cuda.current_stream())
-        used = []
-        with torch.cuda.stream(st):
-            for (log_n, level), rs in batch:
-                slab = self._slab(log_n, level, len(rs))
-                c, d, out = slab
-                for i, r in enumerate(rs):
-                    c[i].copy_(r.c[0], non_blocking=True)
-                    d[i].copy_(r.d[0], non_blocking=True)
-                    r.slot = (slab, i)
-                H.ct_tensor(self.view(log_n, level), c, d, out=out, stream=st)
-                used.append(((log_n, level, len(rs)), slab))
-            ev = torch.cuda.Event()
-            ev.record(st)
+        st.wait_stream(torch.cuda.current_stream())   # the operands were written on the current stream
+        used, jobs = [], []
+        for r in reqs:
+            out = self._out(r.log_n, r.level)
+            used.append(((r.log_n, r.level), out))
+            jobs.append((self.view(r.log_n, r.level), r.c, r.d, out))
+            r.slot = out
+        try:
+            H.ct_tensor_grouped(jobs, stream=st)
+        except Exception:
+            for key, out in used:
+                self._put(key, out)
+            raise
+        ev = torch.cuda.Event()
+        ev.record(st)
         self.peak_held = max(self.peak_held, self.held_bytes())
         return (ev, used, st)
 
@@ -295,13 +316,11 @@ class HipBackend:
     def collect(self, handle, reqs):
         if self.keep_results:
             for r in reqs:
-                slab, i = r.slot
-                r.result = slab[2][i:i + 1].clone()
+                r.result = r.slot.clone()
 
     def release(self, handle):
-        for key, slab in handle[1]:
-            self.pool.setdefault(key, []).append(slab)
-            self.pool.move_to_end(key)
+        for key, out in handle[1]:
+            self._put(key, out)
 
 
 def serve_per_request(requests, backend, clock=time.perf_counter):
@@ -316,14 +335,11 @@ def serve_per_request(requests, backend, clock=time.perf_counter):
         if r.arrival > now:
             time.sleep(r.arrival - now)
         r.arrival = t0 + r.arrival
-        with torch.cuda.stream(st):
-            slab = backend._slab(r.log_n, r.level, 1)
-            c, d, out = slab
-            c[0].copy_(r.c[0], non_blocking=True)
-            d[0].copy_(r.d[0], non_blocking=True)
-            H.ct_tensor(backend.view(r.log_n, r.level), c, d, out=out, stream=st)
+        st.wait_stream(torch.cuda.current_stream())
+        out = backend._out(r.log_n, r.level)
+        H.ct_tensor(backend.view(r.log_n, r.level), r.c, r.d, out=out, stream=st)
         st.synchronize()
         r.t_done = clock()
         r.state = "done"
-        backend.pool.setdefault((r.log_n, r.level, 1), []).append(slab)
+        backend._put((r.log_n, r.level), out)
     return clock() - t0

@@ -67,6 +67,11 @@ def test_status_codes():
     assert L.hentt_dyadic_mul(None, None, None, None, 1, None) == -1
     assert L.hentt_polymul(None, None, None, None, 1, None) == -1
     assert L.hentt_ct_tensor(None, None, None, None, 1, 0, None) == -1
+    assert L.hentt_ct_tensor_grouped(None, 0, 0, None) == 0            # no jobs: nothing to do
+    assert L.hentt_ct_tensor_grouped(None, 1, 0, None) == -1
+    jobs = (H._CtJob * 2)()                                             # zeroed: NULL pointers
+    assert L.hentt_ct_tensor_grouped(jobs, 2, 0, None) == -1
+    assert L.hentt_ct_tensor_grouped(jobs, 2, 4, None) == -1            # unknown flag
     assert L.hentt_ntt_batch(None, 0, 1, None) == -1
     assert L.hentt_tables_destroy(None) == -1
     assert L.hentt_check_canonical(None, None, 1, None, None, None) == -1

@@ -96,6 +96,24 @@ def test_continuous_batching_admits_arrivals_between_steps():
     assert be.max_inflight == 2 and be.inflight == 0
 
 
+def test_full_queue_keeps_two_steps_in_flight():
+    """All requests at t = 0 with the budget full: each step takes at most half
+    the budget, so the second step is launched while the first runs."""
+    clock = Clock()
+    be = FakeBackend(clock, delay=2.0)
+    fp = serve.footprint(14, 4)
+    s = serve.Scheduler(be, budget_bytes=4 * fp, streams=2, clock=clock)
+    reqs = [make_req(i, 0.0) for i in range(8)]
+    for r in reqs:
+        s.submit(r)
+    s.tick()                              # admits 4, launches 2 + 2
+    assert be.launches == 2 and be.inflight == 2
+    assert [sum(len(rids) for _, rids in step) for step in be.groups] == [2, 2]
+    drive(s, clock, [])
+    assert all(r.state == "done" for r in reqs) and s.reserved == 0
+    assert be.launches == 4 and be.max_inflight == 2
+
+
 def test_oversized_request_is_rejected_not_blocking():
     clock = Clock()
     be = FakeBackend(clock)
