@@ -54,6 +54,22 @@ __device__ __forceinline__ void batch_inv_block(uint64_t *p, uint32_t blockStart
   store_global<BATCH_B, BATCH_E, L::LO, L::R>(v, p, RoundMap<BATCH_B, BATCH_E, L::LO, L::R>::lane_part(tid));
 }
 
+// Column accesses whose per-element offset goes into the (wave-uniform, scalar)
+// base address: every element shares the lane's one offset register instead
+// of holding an address register of its own across the butterfly round.
+// The base itself is made opaque first, so that the store side recomputes
+// the element bases instead of keeping the load side's live in SGPRs.
+template <int LOGN, int EC>
+__device__ __forceinline__ const uint64_t *col_elem(const uint64_t *p, int s) {
+  const uint64_t *e = p + ((uint64_t)s << (LOGN - EC));
+  asm volatile("" : "+s"(e));
+  return e;
+}
+__device__ __forceinline__ const uint64_t *opaque_s(const uint64_t *p) {
+  asm volatile("" : "+s"(p));
+  return p;
+}
+
 // Column pass of 2^EC stages (N = 2^(12+EC)) on a tile of 4096 coefficients:
 // 256 lanes x CPL columns each (CPL = 16 / 2^EC, at least 1).
 template <int EC, bool INV>
@@ -65,14 +81,18 @@ __device__ __forceinline__ void batch_cols(uint64_t *p, uint32_t tile, uint32_t 
   for (uint32_t j = 0; j < CPL; ++j) {
     const uint32_t col = (tile * CPL + j) * BATCH_LANES + tid;
     uint64_t v[1 << EC];
-    load_global<LOGN, EC, LO, EC>(v, p, col);
+    const uint64_t *pl = opaque_s(p);
+#pragma unroll
+    for (int s = 0; s < (1 << EC); ++s) v[s] = gload<false>(col_elem<LOGN, EC>(pl, s), col);
     if constexpr (!INV) {
       fwd_round<LOGN, EC, LO, EC>(v, LOGN, 0, col, t, c.m);
     } else {
       inv_round<LOGN, EC, LO, EC>(v, LOGN, 0, col, t, c);
       reduce_inv<EC>(v, c.m);
     }
-    store_global<LOGN, EC, LO, EC>(v, p, col);
+    const uint64_t *ps = opaque_s(p);
+#pragma unroll
+    for (int s = 0; s < (1 << EC); ++s) gstore<false>(const_cast<uint64_t *>(col_elem<LOGN, EC>(ps, s)), col, v[s]);
   }
 }
 

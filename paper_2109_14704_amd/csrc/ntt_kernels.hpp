@@ -529,6 +529,23 @@ struct ProdArgs {
   uint64_t in_sb, out_sb;  // words between consecutive batch entries
 };
 
+// arr[i] for a wave-uniform i < N, as a chain of selects: indexing the
+// kernel-argument array with a loop counter directly made the compiler copy
+// it to scratch and load the pointer from there into VGPRs.
+// Each element passes through an (empty) scalar-register asm first, so the
+// select chain is not folded back into an indexed load.
+template <typename T, int N> __device__ __forceinline__ T pick_ptr(T const (&arr)[N], int i) {
+  T r = arr[0];
+  asm volatile("" : "+s"(r));
+#pragma unroll
+  for (int k = 1; k < N; ++k) {
+    T c = arr[k];
+    asm volatile("" : "+s"(c));
+    r = (i == k) ? c : r;
+  }
+  return r;
+}
+
 template <int MODE, int E>
 __device__ __forceinline__ void products(uint64_t (&X)[ProdShape<MODE>::NIN][1 << E],
                                          uint64_t (&Y)[ProdShape<MODE>::NOUT][1 << E], const LimbConst &c) {
@@ -621,12 +638,12 @@ __device__ __forceinline__ void prod_block(const ProdArgs &a, const Tw *__restri
       // an opaque copy of the table pointer per input: the twiddles are re-read
       // from cache instead of being hoisted out of the loop into VGPRs
       const Tw *tp = opaque(t);
-      load_global<B, E, F::LO, F::R, true>(v, a.in[p] + in_off, RoundMap<B, E, F::LO, F::R>::lane_part(tid));
+      load_global<B, E, F::LO, F::R, true>(v, pick_ptr(a.in, p) + in_off, RoundMap<B, E, F::LO, F::R>::lane_part(tid));
       fwd_block_rounds<B, E, F::LO, F::R>(v, LOGN, lds, tid, blockStart, tp, c.m);
       if constexpr (DO_INV) reduce_for_mont<MODE, E>(v, c.m);
       else reduce_fwd<E>(v, c.m);
     } else {
-      load_global_m0<B, E, true>(v, a.in[p] + in_off, lds, tid);
+      load_global_m0<B, E, true>(v, pick_ptr(a.in, p) + in_off, lds, tid);
     }
     static_for<0, NIN>([&](auto P) {
       if (p == decltype(P)::value) {
@@ -655,9 +672,9 @@ __device__ __forceinline__ void prod_block(const ProdArgs &a, const Tw *__restri
       __syncthreads();  // earlier LDS reads of this workgroup are done
       inv_block_rounds<B, E, 0, E>(v, LOGN, lds, tid, blockStart, opaque(it), c);
       if constexpr (B == LOGN) reduce_inv<E>(v, c.m);
-      store_global<B, E, L::LO, L::R>(v, a.out[o] + out_off, RoundMap<B, E, L::LO, L::R>::lane_part(tid));
+      store_global<B, E, L::LO, L::R>(v, pick_ptr(a.out, o) + out_off, RoundMap<B, E, L::LO, L::R>::lane_part(tid));
     } else {
-      store_global_m0<B, E>(v, a.out[o] + out_off, lds, tid);
+      store_global_m0<B, E>(v, pick_ptr(a.out, o) + out_off, lds, tid);
     }
   }
 }
