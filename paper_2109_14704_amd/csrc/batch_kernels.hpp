@@ -85,7 +85,7 @@ __device__ __forceinline__ void batch_cols(uint64_t *p, uint32_t tile, uint32_t 
 #pragma unroll
     for (int s = 0; s < (1 << EC); ++s) v[s] = gload<false>(col_elem<LOGN, EC>(pl, s), col);
     if constexpr (!INV) {
-      fwd_round<LOGN, EC, LO, EC>(v, LOGN, 0, col, t, c.m);
+      fwd_round<LOGN, EC, LO, EC, 0>(v, LOGN, 0, col, t, c.m);
     } else {
       inv_round<LOGN, EC, LO, EC>(v, LOGN, 0, col, t, c);
       reduce_inv<EC>(v, c.m);

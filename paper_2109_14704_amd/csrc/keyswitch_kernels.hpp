@@ -42,8 +42,8 @@ struct KsArgs {
 __device__ __forceinline__ uint64_t ks_lift(uint64_t x, uint64_t mu, uint64_t q) { return x - mulhi64(x, mu) * q; }
 
 // acc0 += v . key0 R^-1, acc1 += v . key1 R^-1 (mod q, accumulators kept
-// in [0, 2q)) for the words of v (lazy forward outputs below 8q, so that
-// v . key < 8 q^2 < q R) held in the (0, E) map of a 2^B block; key0 at k,
+// in [0, 2q)) for the words of v (lazy forward outputs below 16q, so that
+// v . key < 16 q^2 < q R) held in the (0, E) map of a 2^B block; key0 at k,
 // key1 one prime-row further (`row` blocks of 2^B words).  The two products
 // run one after the other (scheduling barrier) so that only one key array is
 // live.
@@ -141,7 +141,7 @@ __global__ __launch_bounds__(256) void k_ks_cols(KsArgs a, const Tw *__restrict_
   load_global<LOGN, EC, LO, EC, true>(v, a.d + (((uint64_t)b * a.l + j) << LOGN), col);
 #pragma unroll
   for (int s = 0; s < (1 << EC); ++s) v[s] = ks_lift(v[s], mu, m.q);
-  fwd_round<LOGN, EC, LO, EC>(v, LOGN, 0, col, tw + (size_t)t * 2 * (1u << LOGN), m);
+  fwd_round<LOGN, EC, LO, EC, 0>(v, LOGN, 0, col, tw + (size_t)t * 2 * (1u << LOGN), m);
   store_global<LOGN, EC, LO, EC, true>(v, a.e + ((((uint64_t)b * a.l + j) * L1 + t) << LOGN), col);
 }
 

@@ -79,6 +79,22 @@ __device__ __forceinline__ void ct_bfly(uint64_t &X, uint64_t &Y, uint64_t W, ui
   Y = (x + m.q4) - T;
 }
 
+// Forward butterfly of the library's transforms, with the correction of X
+// taken every second stage: values lie in [0, 16q) (q < 2^60, so 16q < 2^64).
+// CORR: X (below 16q) is first brought below 8q, and the outputs lie below
+// 12q; otherwise X must already be below 12q and the outputs lie below 16q.
+// A pass corrects at its even-numbered stages (the first one included), so
+// two uncorrected stages never follow each other and a pass may start from
+// any values below 16q.  T lies in [0, 4q) for any Y < 2^64.
+template <bool CORR>
+__device__ __forceinline__ void ct_bfly16(uint64_t &X, uint64_t &Y, uint64_t W, uint64_t Ws, const ModQ &m) {
+  uint64_t x = X;
+  if constexpr (CORR) x = csubn(X, m.nq4 + m.nq4);  // -8q mod 2^64
+  const uint64_t T = shoup(W, Ws, Y, m.nq);
+  X = x + T;
+  Y = (x + m.q4) - T;
+}
+
 // Inverse (Gentleman-Sande) lazy butterfly after Harvey: X, Y in [0, 4q) on
 // entry and exit; X' = X + Y, Y' = W (X - Y) (mod q).
 __device__ __forceinline__ void gs_bfly(uint64_t &X, uint64_t &Y, uint64_t W, uint64_t Ws, const ModQ &m) {
@@ -93,6 +109,10 @@ __device__ __forceinline__ uint64_t reduce_8q(uint64_t x, const ModQ &m) {
   return csubn(csubn(csubn(x, m.nq4), m.nq2), m.nq);
 }
 __device__ __forceinline__ uint64_t reduce_4q(uint64_t x, const ModQ &m) { return csubn(csubn(x, m.nq2), m.nq); }
+// From [0, 16q) (forward outputs of ct_bfly16 passes) to [0, q).
+__device__ __forceinline__ uint64_t reduce_16q(uint64_t x, const ModQ &m) {
+  return csubn(csubn(csubn(csubn(x, m.nq4 + m.nq4), m.nq4), m.nq2), m.nq);
+}
 
 // Barrett reduction of a 128-bit z < 2^(2k+1) modulo q, 2^(k-1) <= q < 2^k
 // (k <= 60), with mu = floor(2^(2k) / q): quotient estimate

@@ -81,7 +81,11 @@ __device__ __forceinline__ LimbConst ld_lc(const LimbConst *p) {
 // ---------------------------------------------------------------- rounds --
 // Forward stages with global index s = LOGN - LO - R + u, u < R.  Stage s
 // pairs j with j + N/2^(s+1) and uses psi_rev[2^s + (j >> (LOGN - s))].
-template <int B, int E, int LO, int R>
+// P0 >= 0: the library's butterfly (ct_bfly16, values below 16q), P0 being
+// the parity of the round's first stage within its pass (a stage corrects X
+// when its index within the pass is even).  P0 < 0: the classic butterfly
+// (every stage corrects, values below 8q), for the reference designs.
+template <int B, int E, int LO, int R, int P0 = -1>
 __device__ __forceinline__ void fwd_round(uint64_t (&x)[1 << E], uint32_t logn, uint32_t blockStart,
                                           uint32_t lanePart, const Tw* __restrict__ tw, const ModQ &m) {
   using M = RoundMap<B, E, LO, R>;
@@ -97,7 +101,9 @@ __device__ __forceinline__ void fwd_round(uint64_t (&x)[1 << E], uint32_t logn, 
       for (int k = 0; k < (1 << R); ++k) {
         if (k & h) continue;
         const Tw w = ld_tw(tw, base + (k >> (R - u)));
-        ct_bfly(x[(g << R) + k], x[(g << R) + k + h], w.w, w.ws, m);
+        if constexpr (P0 < 0) ct_bfly(x[(g << R) + k], x[(g << R) + k + h], w.w, w.ws, m);
+        else if (((P0 + u) & 1) == 0) ct_bfly16<true>(x[(g << R) + k], x[(g << R) + k + h], w.w, w.ws, m);
+        else ct_bfly16<false>(x[(g << R) + k], x[(g << R) + k + h], w.w, w.ws, m);
       }
     }
   }
@@ -237,10 +243,10 @@ __device__ __forceinline__ void load_global_m0(uint64_t (&x)[1 << E], const uint
 #endif
 }
 
-// Canonical reductions of forward outputs ([0, 8q)) and inverse outputs ([0, 4q)).
+// Canonical reductions of forward outputs ([0, 16q)) and inverse outputs ([0, 4q)).
 template <int E> __device__ __forceinline__ void reduce_fwd(uint64_t (&x)[1 << E], const ModQ &m) {
 #pragma unroll
-  for (int s = 0; s < (1 << E); ++s) x[s] = reduce_8q(x[s], m);
+  for (int s = 0; s < (1 << E); ++s) x[s] = reduce_16q(x[s], m);
 }
 template <int E> __device__ __forceinline__ void reduce_inv(uint64_t (&x)[1 << E], const ModQ &m) {
 #pragma unroll
@@ -251,13 +257,14 @@ template <int E> __device__ __forceinline__ void reduce_inv(uint64_t (&x)[1 << E
 // Forward rounds over the block bits [0, LO+R) (the first round covers
 // [LO, LO+R)), starting from registers already loaded with the first round's
 // map.  Ends with the lane holding the last round (LO = 0) map in registers,
-// i.e. 2^E consecutive elements, values in [0, 4q).
-template <int B, int E, int LO, int R>
+// i.e. 2^E consecutive elements, values in [0, 16q).  P: parity of the
+// round's first stage within the block pass.
+template <int B, int E, int LO, int R, int P = 0>
 __device__ __forceinline__ void fwd_block_rounds(uint64_t (&x)[1 << E], uint32_t logn, uint64_t* lds, uint32_t tid,
                                                  uint32_t blockStart, const Tw* __restrict__ tw, const ModQ &m) {
   using M = RoundMap<B, E, LO, R>;
   const uint32_t lp = M::lane_part(tid);
-  fwd_round<B, E, LO, R>(x, logn, blockStart, lp, tw, m);
+  fwd_round<B, E, LO, R, P>(x, logn, blockStart, lp, tw, m);
   if constexpr (LO > 0) {
     constexpr int R2 = E;
     constexpr int LO2 = LO - R2;
@@ -266,7 +273,7 @@ __device__ __forceinline__ void fwd_block_rounds(uint64_t (&x)[1 << E], uint32_t
     __syncthreads();
     using M2 = RoundMap<B, E, LO2, R2>;
     load_lds<B, E, LO2, R2>(x, lds, M2::lane_part(tid));
-    fwd_block_rounds<B, E, LO2, R2>(x, logn, lds, tid, blockStart, tw, m);
+    fwd_block_rounds<B, E, LO2, R2, (P + R) & 1>(x, logn, lds, tid, blockStart, tw, m);
   }
 }
 
@@ -375,7 +382,7 @@ __device__ __forceinline__ void col_pass(const uint64_t *src, uint64_t *dst, uin
   uint64_t v[1 << E];
   load_global<LOGN, E, LO, E, true>(v, src, col);
   if constexpr (!INV) {
-    fwd_round<LOGN, E, LO, E>(v, LOGN, 0, col, t, c.m);
+    fwd_round<LOGN, E, LO, E, 0>(v, LOGN, 0, col, t, c.m);
   } else {
     inv_round<LOGN, E, LO, E>(v, LOGN, 0, col, t, c);
     reduce_inv<E>(v, c.m);
@@ -403,8 +410,8 @@ __device__ __forceinline__ void col_pass2(const uint64_t *src, uint64_t *dst, ui
     v1[s] = w.y;
   }
   if constexpr (!INV) {
-    fwd_round<LOGN, E, LO, E>(v0, LOGN, 0, col, t, c.m);
-    fwd_round<LOGN, E, LO, E>(v1, LOGN, 0, col, t, c.m);
+    fwd_round<LOGN, E, LO, E, 0>(v0, LOGN, 0, col, t, c.m);
+    fwd_round<LOGN, E, LO, E, 0>(v1, LOGN, 0, col, t, c.m);
   } else {
     inv_round<LOGN, E, LO, E>(v0, LOGN, 0, col, t, c);
     inv_round<LOGN, E, LO, E>(v1, LOGN, 0, col, t, c);
@@ -583,11 +590,11 @@ __device__ __forceinline__ void products_mont(uint64_t (&X)[ProdShape<MODE>::NIN
   }
 }
 
-// Forward outputs ([0, 8q)) brought to the factor range of products_mont.
+// Forward outputs ([0, 16q)) brought to the factor range of products_mont.
 template <int MODE, int E> __device__ __forceinline__ void reduce_for_mont(uint64_t (&x)[1 << E], const ModQ &m) {
 #pragma unroll
   for (int s = 0; s < (1 << E); ++s) {
-    x[s] = csubn(x[s], m.nq4);
+    x[s] = csubn(csubn(x[s], m.nq4 + m.nq4), m.nq4);
     if constexpr (MODE == PROD_TENSOR) x[s] = csubn(x[s], m.nq2);
   }
 }

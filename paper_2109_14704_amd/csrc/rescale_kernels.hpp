@@ -89,7 +89,7 @@ __global__ __launch_bounds__(256) void k_rs_cols(RsArgs a, const Tw *__restrict_
   load_global<LOGN, EC, LO, EC, true>(v, a.tl + ((uint64_t)b << LOGN), col);
 #pragma unroll
   for (int s = 0; s < (1 << EC); ++s) v[s] = rs_prologue(v[s], a.qL, a.h, r, m.q);
-  fwd_round<LOGN, EC, LO, EC>(v, LOGN, 0, col, tw + (size_t)i * 2 * (1u << LOGN), m);
+  fwd_round<LOGN, EC, LO, EC, 0>(v, LOGN, 0, col, tw + (size_t)i * 2 * (1u << LOGN), m);
   store_global<LOGN, EC, LO, EC, true>(v, a.out + (((uint64_t)b * a.L + i) << LOGN), col);
 }
 

@@ -1,6 +1,7 @@
 // CPU property test of the device modular arithmetic (modarith.hpp built for
-// the host).  Checks Algorithm 1's contract (inputs and outputs in [0, 4q),
-// X' = X + W Y, Y' = X - W Y mod q), the inverse butterfly's [0, 2q) contract,
+// the host).  Checks the forward butterflies' contracts (the classic one in
+// [0, 8q) and the library's alternating one in [0, 16q); X' = X + W Y,
+// Y' = X - W Y mod q), the inverse butterfly's [0, 4q) contract,
 // the Barrett/Shoup/mad_mod products and the Montgomery reduction against
 // exact 128-bit arithmetic.
 #include <stdint.h>
@@ -53,6 +54,20 @@ int main(int argc, char **argv) {
     uint64_t wy = mm(W, Yb % q, q);
     EXPECT(x1 < q8 && y1 < q8, "ct range\n");
     EXPECT(x1 % q == (X % q + wy) % q && y1 % q == (X % q + q - wy) % q, "ct value\n");
+    // the library's forward butterfly, lazy range [0, 16q), correcting every
+    // second stage: corrected from X < 16q to outputs < 12q, uncorrected from
+    // X < 12q to outputs < 16q
+    uint64_t q16 = 16 * q, q12 = 12 * q, Yw = (it % 5 == 1) ? ~0ull : g();
+    uint64_t Xc = (it % 3 == 1) ? q16 - 1 : g() % q16, Xu = (it % 3 == 2) ? q12 - 1 : g() % q12;
+    uint64_t xc = Xc, yc = Yw, xu = Xu, yu = Yw;
+    ct_bfly16<true>(xc, yc, W, Ws, m);
+    ct_bfly16<false>(xu, yu, W, Ws, m);
+    uint64_t wyw = mm(W, Yw % q, q);
+    EXPECT(xc < q12 && yc < q12, "ct16 corrected range\n");
+    EXPECT(xu < q16 && yu < q16, "ct16 uncorrected range\n");
+    EXPECT(xc % q == (Xc % q + wyw) % q && yc % q == (Xc % q + q - wyw) % q, "ct16 corrected value\n");
+    EXPECT(xu % q == (Xu % q + wyw) % q && yu % q == (Xu % q + q - wyw) % q, "ct16 uncorrected value\n");
+    EXPECT(reduce_16q(Xc, m) == Xc % q, "reduce_16q\n");
     // inverse butterfly, lazy range [0, 4q)
     uint64_t Xi = (it % 7 == 0) ? 4 * q - 1 : g() % (4 * q), Yi = (it % 6 == 0) ? 4 * q - 1 : g() % (4 * q);
     uint64_t x2 = Xi, y2 = Yi;
@@ -84,6 +99,10 @@ int main(int argc, char **argv) {
     uint64_t x4 = mont_mad(a2, d2, c2, b2, q, qinv);
     u128 T4 = (u128)a2 * d2 + (u128)c2 * b2;
     EXPECT(x4 < 2 * q && (((u128)x4 << 64) % q) == T4 % q, "mont_mad q=%llx\n", (unsigned long long)q);
+    // the key switch's products: a forward output below 16q times a key word below q
+    uint64_t a16 = (it % 13 == 1) ? q16 - 1 : g() % q16, kq = (it % 14 == 1) ? q - 1 : g() % q;
+    uint64_t x7 = mont_mul(a16, kq, q, qinv);
+    EXPECT(x7 < 2 * q && (((u128)x7 << 64) % q) == ((u128)a16 * kq) % q, "mont_mul 16q x q\n");
     // the reduction itself at the edge T = q R - 1 and at T = 0
     uint64_t x5 = redc(q - 1, ~0ull, q, qinv), x6 = redc(0, 0, q, qinv);
     EXPECT(x5 < 2 * q && (((u128)x5 << 64) % q) == ((((u128)(q - 1)) << 64) | ~0ull) % q && x6 == 0, "redc edges\n");
