@@ -505,7 +505,7 @@ def bench_ladder(args):
                (H.VARIANT_STAGED_R4, "column pass + LDS blocks of 4096, radix-4 rounds"),
                (H.VARIANT_STAGED_R8, "column pass + LDS blocks of 4096, radix-8 rounds (the paper's best)"),
                (H.VARIANT_STAGED_R16, "column pass + LDS blocks of 4096, radix-16 rounds"),
-               (H.VARIANT_LIBRARY, "library: 5-stage radix-32 column pass + radix-16 LDS blocks of 1024")]
+               (H.VARIANT_LIBRARY, "library: default instance (%s)" % H.tune_describe("fwd", logn, 0))]
     rows = []
     for v, desc in designs:
         for _ in range(max(2, args.warmup // 4)):

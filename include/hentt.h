@@ -353,10 +353,11 @@ int hentt_prof_enable(int on);
 int hentt_prof_count(void);
 int hentt_prof_get(uint32_t i, char *name, uint32_t name_len, double *total_ms, uint32_t *launches);
 
-/* Stage split of the launch plan at N = 2^log_n: how many butterfly stages
- * the column pass of a plain transform (transform_cols) and of a fused
- * product (product_cols) performs; 0 means the transform runs whole in one
- * workgroup.  Host-only, no device work. */
+/* Stage split of the default instances at N = 2^log_n: how many butterfly
+ * stages the column pass of a plain transform (transform_cols) and of the
+ * fused dyadic product (product_cols) performs; 0 means the transform runs
+ * whole in one workgroup.  Tuned instances (hentt_tune_*) and the tensor
+ * product may split differently.  Host-only, no device work. */
 int hentt_stage_split(uint32_t log_n, uint32_t *transform_cols, uint32_t *product_cols);
 
 /* Autotuning (the tuning constants of section III-B, chosen by measurement):

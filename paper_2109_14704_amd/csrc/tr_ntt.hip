@@ -72,10 +72,10 @@ struct TrCand {
 const TrCand c6[] = {W(6)}, c7[] = {W(7)}, c8[] = {W(8)}, c9[] = {W(9)}, c10[] = {W(10)}, c11[] = {W(11)},
              c12[] = {W(12)};
 const TrCand c13[] = {W(13), T(13, 1, 4)};
-const TrCand c14[] = {W(14), T(14, 2, 4), T(14, 2, 3)};
+const TrCand c14[] = {T(14, 2, 3), W(14), T(14, 2, 4)};
 const TrCand c15[] = {T(15, 5, 4), T(15, 4, 4), T(15, 3, 4), T(15, 5, 3), T(15, 4, 3)};
-const TrCand c16[] = {T(16, 5, 4), T(16, 4, 4), T(16, 5, 3), T(16, 4, 3)};
-const TrCand c17[] = {T(17, 4, 4), T(17, 5, 4), T(17, 5, 3)};
+const TrCand c16[] = {T(16, 5, 3), T(16, 5, 4), T(16, 4, 4), T(16, 4, 3)};
+const TrCand c17[] = {T(17, 5, 3), T(17, 5, 4), T(17, 4, 4)};
 #undef W
 #undef T
 struct TrList {

@@ -14,9 +14,11 @@
 namespace hentt_rt {
 namespace {
 
-// Column stages of the grouped product at N = 2^log_n (the split of the
-// single-job product's default instance; 0 = one kernel per block of N).
-constexpr int grouped_pec(int log_n) { return log_n >= 15 ? 5 : log_n == 14 ? 2 : log_n == 13 ? 1 : 0; }
+// Column stages and log2 words per lane of the grouped product at N = 2^log_n
+// (the single-job tensor's default instance; 0 column stages = one kernel per
+// block of N).
+constexpr int grouped_pec(int log_n) { return log_n >= 14 ? (log_n == 14 ? 3 : 5) : log_n == 13 ? 1 : 0; }
+constexpr int grouped_pe(int log_n) { return log_n == 15 ? 2 : 3; }
 
 struct HostJob {
   const uint64_t *c, *d;
@@ -32,7 +34,7 @@ uint64_t ws_words(const HostJob &h) { return 4ull * h.batch * ((uint64_t)h.t->li
 // ws: workspace of sum(ws_words) words when the forward column pass runs.
 template <int LOGN>
 int launch_group(const HostJob *jobs, uint32_t n, bool in_coeff, bool out_coeff, uint64_t *ws, hipStream_t st) {
-  constexpr int PEC = grouped_pec(LOGN), PE = 3;
+  constexpr int PEC = grouped_pec(LOGN), PE = grouped_pe(LOGN);
   constexpr int B = PEC ? LOGN - PEC : LOGN;
   GroupTable g{};
   g.n = n;

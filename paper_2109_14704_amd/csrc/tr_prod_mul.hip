@@ -5,15 +5,15 @@
 
 namespace hentt_rt {
 namespace {
-#define D(n, pec) {launch_prod_cfg<n, PROD_MUL, pec, 4, true>, pec, "column stages " #pec ", block words per lane 2^4"}
+#define D(n, pec, e) {launch_prod_cfg<n, PROD_MUL, pec, e, true>, pec, "column stages " #pec ", block words per lane 2^" #e}
 #define C(n, pec, e) {launch_prod_cfg<n, PROD_MUL, pec, e, false>, pec, "column stages " #pec ", block words per lane 2^" #e}
-const ProdCand m6[] = {D(6, 0)}, m7[] = {D(7, 0)}, m8[] = {D(8, 0)}, m9[] = {D(9, 0)}, m10[] = {D(10, 0)},
-               m11[] = {D(11, 0)}, m12[] = {D(12, 0)};
-const ProdCand m13[] = {D(13, 1), C(13, 0, 4)};
-const ProdCand m14[] = {D(14, 2), C(14, 2, 3), C(14, 3, 4)};
-const ProdCand m15[] = {D(15, 5), C(15, 4, 4), C(15, 5, 3), C(15, 4, 3)};
-const ProdCand m16[] = {D(16, 5), C(16, 4, 4), C(16, 5, 3)};
-const ProdCand m17[] = {D(17, 5), C(17, 4, 4)};
+const ProdCand m6[] = {D(6, 0, 4)}, m7[] = {D(7, 0, 4)}, m8[] = {D(8, 0, 4)}, m9[] = {D(9, 0, 4)},
+               m10[] = {D(10, 0, 4)}, m11[] = {D(11, 0, 4)}, m12[] = {D(12, 0, 4)};
+const ProdCand m13[] = {D(13, 0, 4), C(13, 1, 4)};
+const ProdCand m14[] = {D(14, 2, 3), C(14, 2, 4), C(14, 3, 4)};
+const ProdCand m15[] = {D(15, 5, 3), C(15, 5, 4), C(15, 4, 4), C(15, 4, 3)};
+const ProdCand m16[] = {D(16, 5, 3), C(16, 5, 4), C(16, 4, 4)};
+const ProdCand m17[] = {D(17, 5, 4), C(17, 4, 4)};
 #undef D
 #undef C
 const ProdList k_mul[] = {HENTT_PROD_LIST(m6),  HENTT_PROD_LIST(m7),  HENTT_PROD_LIST(m8),  HENTT_PROD_LIST(m9),
