@@ -75,13 +75,18 @@ __global__ __launch_bounds__(1 << (LOGN - E)) void k_rs_whole(RsArgs a, const Tw
 }
 
 // Column pass (first EC forward stages) of t_i from the last limb, into out.
+// Batch-entry-major order: the L units of one batch entry read the same
+// last-limb columns one after another, so all but the first read hit the
+// XCD's L2 (tile t of every unit lands on the same XCD when the tile count is
+// a multiple of 8); limb-major order re-read the whole batch's last limbs
+// from HBM or the MALL once per limb.
 template <int LOGN, int EC>
 __global__ __launch_bounds__(256) void k_rs_cols(RsArgs a, const Tw *__restrict__ tw,
                                                  const LimbConst *__restrict__ lc) {
   constexpr uint32_t tiles = (1u << (LOGN - EC)) / 256;
   constexpr int LO = LOGN - EC;
-  uint32_t b, i;
-  rs_unit(blockIdx.x / tiles, a.batch, b, i);
+  const uint32_t u = blockIdx.x / tiles;
+  const uint32_t b = u / a.L, i = u % a.L;
   const uint32_t col = (blockIdx.x % tiles) * 256 + threadIdx.x;
   const ModQ m = lc[i].m;
   const RsLimb r = a.rs[i];
