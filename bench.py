@@ -441,6 +441,8 @@ def bench_batched(args):
               "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True,
               "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic"}
     result.update({k: v for k, v in head.items() if k not in ("value", "unit", "ms_per_step")})
+    from paper_2109_14704_amd import roofline as R
+    result["source_digest"] = R.source_digest()     # identifies the kernel sources the line was measured on
     if len(names) > 1:
         result["workloads"] = {nm: results[nm] for nm in names[1:]}
     if measured:

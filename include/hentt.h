@@ -339,7 +339,10 @@ int hentt_graph_destroy(hentt_graph *g);
  * kept after use and reused by later calls on the same device and stream.
  * hentt_pool_bytes reports the bytes the pool holds; hentt_pool_trim waits
  * for the streams of the idle buffers and frees them (buffers of calls still
- * being enqueued by other threads are kept). */
+ * being enqueued by other threads are kept).  Environment: with
+ * HENTT_POOL_MAX_BYTES=<bytes> (read once), a call that would grow the pool
+ * past that many bytes first trims the idle buffers (a soft cap: a single
+ * buffer larger than the cap is still allocated). */
 int hentt_pool_bytes(uint64_t *bytes);
 int hentt_pool_trim(void);
 

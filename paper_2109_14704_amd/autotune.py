@@ -17,6 +17,10 @@ Tuned knobs:
 
 The cache is keyed by device architecture, a digest of the kernel sources
 (a tuned choice is void once the kernels change) and the tuned shape.
+
+Environment: HENTT_TUNE_CACHE (cache file), HENTT_TUNE = "cached" (default:
+use a cached choice, tune on a miss), "force" (tune again and overwrite the
+cache) or "off" (no timing: the library defaults).
 """
 import json
 import os
@@ -34,6 +38,13 @@ class ParityError(RuntimeError):
 
 def cache_path():
     return os.environ.get("HENTT_TUNE_CACHE", _CACHE)
+
+
+def tune_mode():
+    m = os.environ.get("HENTT_TUNE", "cached")
+    if m not in ("cached", "force", "off"):
+        raise ValueError("HENTT_TUNE must be cached, force or off, not %r" % m)
+    return m
 
 
 def _arch():
@@ -116,6 +127,12 @@ def persistent_grid(plan, data, candidates=None, check=None, force=False):
     plan's device tensors (restored to their contents on return);
     check(outputs) -> bool: optional verification of the default candidate's
     outputs.  Returns (workgroups, lookahead percent, group units)."""
+    mode = tune_mode()
+    if mode == "off":
+        plan.set_grid(0)
+        plan.set_schedule(200, 8)
+        return plan.info()["grid"], 200, 8
+    force = force or mode == "force"
     info = plan.info()
     key = "grid/%s/%s/units%d/tiles%d" % (_arch(), source_digest(), info["units"], info["tiles"])
     cache = _load()
@@ -154,6 +171,11 @@ def kernel_config(op, tables, run, data, batch_units, check=None, force=False):
     `data` is restored to its contents on entry."""
     import paper_2109_14704_amd as H
     cls = H.shape_class(batch_units)
+    mode = tune_mode()
+    if mode == "off":
+        H.tune_select(op, tables.log_n, cls, 0)
+        return H.tune_describe(op, tables.log_n, 0)
+    force = force or mode == "force"
     key = "kernel/%s/%s/%s/logn%d/%s" % (_arch(), source_digest(), op, tables.log_n, cls)
     n = H.tune_count(op, tables.log_n)
     cache = _load()

@@ -2,6 +2,7 @@
 // checks and the plans of uneven batches.  The kernel families are dispatched
 // from their own translation units (tr_*.hip).
 #include <hip/hip_runtime.h>
+#include <dlfcn.h>
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -57,6 +58,65 @@ std::mutex g_pool_mu;
 std::vector<PoolEntry> g_pool;
 }  // namespace
 
+// Frees the idle buffers after waiting for the streams that last used them
+// (caller holds g_pool_mu).
+static void pool_trim_locked() {
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  std::vector<PoolEntry> keep;
+  for (auto &e : g_pool) {
+    if (e.busy) {
+      keep.push_back(e);
+      continue;
+    }
+    // queued work may still use the buffer: wait for its stream first
+    (void)hipSetDevice(e.device);
+    (void)hipStreamSynchronize(e.stream);
+    (void)hipFree(e.ptr);
+  }
+  (void)hipSetDevice(cur);
+  g_pool.swap(keep);
+}
+
+// Soft cap on the pool's bytes from HENTT_POOL_MAX_BYTES (0 or unset: none).
+static uint64_t pool_cap() {
+  static const uint64_t cap = [] {
+    const char *v = getenv("HENTT_POOL_MAX_BYTES");
+    return v ? strtoull(v, nullptr, 10) : 0ull;
+  }();
+  return cap;
+}
+
+namespace {
+typedef int (*roctx_push_fn)(const char *);
+typedef int (*roctx_pop_fn)();
+struct Roctx {
+  roctx_push_fn push = nullptr;
+  roctx_pop_fn pop = nullptr;
+};
+const Roctx &roctx() {
+  static const Roctx r = [] {
+    Roctx x;
+    const char *v = getenv("HENTT_ROCTX");
+    if (!v || strcmp(v, "1") != 0) return x;
+    void *h = dlopen("librocprofiler-sdk-roctx.so.1", RTLD_NOW | RTLD_LOCAL);
+    if (!h) return x;
+    x.push = (roctx_push_fn)dlsym(h, "roctxRangePushA");
+    x.pop = (roctx_pop_fn)dlsym(h, "roctxRangePop");
+    if (!x.push || !x.pop) x = Roctx{};
+    return x;
+  }();
+  return r;
+}
+}  // namespace
+
+ApiRange::ApiRange(const char *name) : on(roctx().push != nullptr) {
+  if (on) roctx().push(name);
+}
+ApiRange::~ApiRange() {
+  if (on) roctx().pop();
+}
+
 int pool_get(size_t bytes, hipStream_t stream, void **out) {
   int dev = 0;
   HIPCHK(hipGetDevice(&dev));
@@ -72,6 +132,11 @@ int pool_get(size_t bytes, hipStream_t stream, void **out) {
     g_pool[best].busy = true;
     *out = g_pool[best].ptr;
     return HENTT_OK;
+  }
+  if (const uint64_t cap = pool_cap()) {
+    uint64_t held = 0;
+    for (auto &pe : g_pool) held += pe.bytes;
+    if (held + bytes > cap) pool_trim_locked();  // idle buffers go before the pool grows past the cap
   }
   void *p = nullptr;
   hipError_t e = hipMalloc(&p, bytes);
@@ -631,6 +696,7 @@ int hentt_tables_device_ptrs(const hentt_tables *t, const uint64_t **fwd, const 
 
 int hentt_check_canonical(const hentt_tables *t, const uint64_t *x, uint32_t batch, uint64_t *bad_words,
                           uint64_t *first_bad, void *stream) {
+  ApiRange range_("hentt_check_canonical");
   if (!t || !x || batch == 0) return HENTT_EINVAL;
   const uint32_t ln = t->s->log_n;
   const uint32_t tiles = ln > 11 ? (1u << (ln - 11)) : 1u;
@@ -655,16 +721,19 @@ int hentt_check_canonical(const hentt_tables *t, const uint64_t *x, uint32_t bat
 }
 
 int hentt_ntt_fwd(const hentt_tables *t, uint64_t *x, uint32_t batch, void *stream) {
+  ApiRange range_("hentt_ntt_fwd");
   if (!t || !x || batch == 0) return HENTT_EINVAL;
   return run_transform(t, x, batch, (hipStream_t)stream, false);
 }
 
 int hentt_ntt_inv(const hentt_tables *t, uint64_t *x, uint32_t batch, void *stream) {
+  ApiRange range_("hentt_ntt_inv");
   if (!t || !x || batch == 0) return HENTT_EINVAL;
   return run_transform(t, x, batch, (hipStream_t)stream, true);
 }
 
 int hentt_ntt_fwd_variant(const hentt_tables *t, uint64_t *x, uint32_t batch, int variant, void *stream) {
+  ApiRange range_("hentt_ntt_fwd_variant");
   if (!t || !x || batch == 0) return HENTT_EINVAL;
   return run_fwd_variant(t, x, batch, variant, (hipStream_t)stream);
 }
@@ -684,6 +753,7 @@ extern "C" {
 
 int hentt_rescale(const hentt_tables *t, const uint64_t *c, uint64_t *out, uint32_t batch, uint32_t flags,
                   void *stream) {
+  ApiRange range_("hentt_rescale");
   if (!t || !c || !out || batch == 0 || t->limbs < 2) return HENTT_EINVAL;
   const bool ntt = flags == (HENTT_IN_NTT | HENTT_OUT_NTT);
   if (!ntt && flags != 0) return HENTT_EINVAL;
@@ -695,6 +765,7 @@ int hentt_rescale(const hentt_tables *t, const uint64_t *c, uint64_t *out, uint3
 
 int hentt_ct_matmul(const hentt_tables *t, const uint64_t *A, const uint64_t *B, uint64_t *C, uint32_t m, uint32_t n,
                     uint32_t k, void *stream) {
+  ApiRange range_("hentt_ct_matmul");
   if (!t || !A || !B || !C || m == 0 || n == 0 || k == 0) return HENTT_EINVAL;
   const uint64_t P = (uint64_t)t->limbs << t->s->log_n;
   const Span c = span(C, (uint64_t)m * n * 3 * P);
@@ -705,6 +776,7 @@ int hentt_ct_matmul(const hentt_tables *t, const uint64_t *A, const uint64_t *B,
 
 int hentt_relin(const hentt_tables *t, const uint64_t *c, const uint64_t *ksk, uint64_t *out, uint32_t batch,
                 void *stream) {
+  ApiRange range_("hentt_relin");
   if (!t || !c || !ksk || !out || batch == 0 || t->limbs < 2) return HENTT_EINVAL;
   const uint64_t N = 1ull << t->s->log_n, l = t->limbs - 1;
   const Span o = span(out, batch * 2 * l * N);
@@ -714,6 +786,7 @@ int hentt_relin(const hentt_tables *t, const uint64_t *c, const uint64_t *ksk, u
 
 int hentt_dyadic_mul(const hentt_tables *t, const uint64_t *a, const uint64_t *b, uint64_t *out, uint32_t batch,
                      void *stream) {
+  ApiRange range_("hentt_dyadic_mul");
   if (!t || !a || !b || !out || batch == 0) return HENTT_EINVAL;
   const uint64_t words = (uint64_t)batch * t->limbs << t->s->log_n;
   const Span o = span(out, words);
@@ -729,6 +802,7 @@ int hentt_dyadic_mul(const hentt_tables *t, const uint64_t *a, const uint64_t *b
 
 int hentt_polymul(const hentt_tables *t, const uint64_t *a, const uint64_t *b, uint64_t *out, uint32_t batch,
                   void *stream) {
+  ApiRange range_("hentt_polymul");
   if (!t || !a || !b || !out || batch == 0) return HENTT_EINVAL;
   const uint64_t words = (uint64_t)batch * t->limbs << t->s->log_n;
   const Span o = span(out, words);
@@ -743,6 +817,7 @@ int hentt_polymul(const hentt_tables *t, const uint64_t *a, const uint64_t *b, u
 
 int hentt_ct_tensor(const hentt_tables *t, const uint64_t *c, const uint64_t *d, uint64_t *out, uint32_t batch,
                     uint32_t flags, void *stream) {
+  ApiRange range_("hentt_ct_tensor");
   if (!t || !c || !d || !out || batch == 0 || (flags & ~3u)) return HENTT_EINVAL;
   const uint64_t NL = (uint64_t)t->limbs << t->s->log_n;
   const Span o = span(out, 3 * NL * batch);
@@ -788,6 +863,7 @@ int hentt_batch_plan_info(const hentt_batch_plan *p, uint32_t *units, uint32_t *
 }
 
 int hentt_batch_plan_run(hentt_batch_plan *p, void *stream) {
+  ApiRange range_("hentt_batch_plan_run");
   if (!p) return HENTT_EINVAL;
   hipStream_t st = (hipStream_t)stream;
   int rc = plan_launch(p, st);
@@ -838,6 +914,7 @@ int hentt_batch_graph_create(hentt_batch_plan *p, hentt_graph **out) {
 }
 
 int hentt_graph_launch(hentt_graph *g, void *stream) {
+  ApiRange range_("hentt_graph_launch");
   if (!g) return HENTT_EINVAL;
   HIPCHK(hipGraphLaunch(g->exec, (hipStream_t)stream));
   HIPCHK(hipEventRecord(g->plan->done, (hipStream_t)stream));  // hentt_batch_plan_status waits for this replay
@@ -854,6 +931,7 @@ int hentt_graph_destroy(hentt_graph *g) {
 }
 
 int hentt_ntt_batch(const hentt_job *jobs, uint32_t njobs, int dir, void *stream) {
+  ApiRange range_("hentt_ntt_batch");
   if (!jobs || njobs == 0 || (dir != 1 && dir != -1)) return HENTT_EINVAL;
   for (uint32_t j = 0; j < njobs; ++j)
     if (!jobs[j].t) return HENTT_EINVAL;
@@ -938,21 +1016,7 @@ int hentt_tune_get(int op, uint32_t log_n, uint32_t cls, uint32_t *choice) {
 
 int hentt_pool_trim(void) {
   std::lock_guard<std::mutex> lk(g_pool_mu);
-  int cur = 0;
-  (void)hipGetDevice(&cur);
-  std::vector<PoolEntry> keep;
-  for (auto &e : g_pool) {
-    if (e.busy) {
-      keep.push_back(e);
-      continue;
-    }
-    // queued work may still use the buffer: wait for its stream first
-    (void)hipSetDevice(e.device);
-    (void)hipStreamSynchronize(e.stream);
-    (void)hipFree(e.ptr);
-  }
-  (void)hipSetDevice(cur);
-  g_pool.swap(keep);
+  pool_trim_locked();
   return HENTT_OK;
 }
 

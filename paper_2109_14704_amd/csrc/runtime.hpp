@@ -93,6 +93,16 @@ struct LaunchTimer {
   }
 };
 
+// ------------------------------------------------------------ roctx ranges
+// With HENTT_ROCTX=1 in the environment (read once), the compute entry points
+// are bracketed by roctx ranges named after them (rocprofv3 --marker-trace);
+// the roctx library is opened on first use, and without it nothing happens.
+struct ApiRange {
+  bool on;
+  explicit ApiRange(const char *name);
+  ~ApiRange();
+};
+
 // ------------------------------------------------------------ launch plans
 // Every operation has, per N, a list of compiled kernel instances (stage
 // split, words per lane); instance 0 is the measured default and the

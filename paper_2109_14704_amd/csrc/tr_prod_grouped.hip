@@ -174,6 +174,7 @@ int check_overlaps(const std::vector<HostJob> &jobs) {
 using namespace hentt_rt;
 
 extern "C" int hentt_ct_tensor_grouped(const hentt_ct_job *jobs, uint32_t njobs, uint32_t flags, void *stream) {
+  ApiRange range_("hentt_ct_tensor_grouped");
   if (njobs == 0) return HENTT_OK;
   if (!jobs || (flags & ~3u)) return HENTT_EINVAL;
   std::vector<HostJob> hj(njobs);

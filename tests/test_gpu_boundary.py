@@ -172,3 +172,36 @@ def test_pool_trim_releases_idle_workspace(gpu):
     p2 = H.polymul(t, a, b)                            # allocates again
     assert torch.equal(p1, p2)
     torch.cuda.synchronize()
+
+
+def test_pool_soft_cap_from_environment(gpu):
+    """HENTT_POOL_MAX_BYTES (read once per process, so in a child process):
+    two polymuls on two streams leave two 8 MiB workspaces in the pool
+    without a cap, and one with a 12 MiB cap (the idle buffer is trimmed
+    before the second allocation)."""
+    import os
+    import subprocess
+    import sys
+    print("case pool soft cap", flush=True)
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = (
+        "import sys; sys.path.insert(0, %r); sys.path.insert(0, %r)\n"
+        "import torch, workloads, paper_2109_14704_amd as H\n"
+        "t = H.Tables(15, workloads.moduli('ckks_level')[:4])\n"
+        "A = torch.zeros((4, 4, 1 << 15), dtype=torch.int64, device='cuda:0')\n"
+        "s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()\n"
+        "H.polymul(t, A, A, stream=s1); torch.cuda.synchronize(); b1 = H.pool_bytes()\n"
+        "H.polymul(t, A, A, stream=s2); torch.cuda.synchronize(); b2 = H.pool_bytes()\n"
+        "print(b1, b2)\n" % (root, os.path.join(root, "tests")))
+    ws = 2 * 4 * 4 * (1 << 15) * 8          # two inputs after the forward column pass
+    got = {}
+    for cap in (None, ws * 3 // 2):
+        env = dict(os.environ)
+        env.pop("HENTT_POOL_MAX_BYTES", None)
+        if cap:
+            env["HENTT_POOL_MAX_BYTES"] = str(cap)
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+        assert r.returncode == 0, r.stderr[-2000:]
+        got[cap] = [int(v) for v in r.stdout.split()[-2:]]
+    assert got[None] == [ws, 2 * ws], got
+    assert got[ws * 3 // 2] == [ws, ws], got

@@ -126,3 +126,26 @@ def test_tuning_abi_host_only():
     assert L.hentt_tune_select(0, 15, 3, 0) == -1                      # no such class
     assert L.hentt_tune_select(0, 15, 0, H.tune_count("fwd", 15)) == -1
     assert L.hentt_tune_describe(0, 15, 0, None, 0, None) == -1
+
+
+def test_roctx_ranges_and_tune_mode_host_only(tmp_path):
+    """HENTT_ROCTX=1 opens the roctx library and brackets entry points (an
+    invalid call still returns its status); HENTT_TUNE accepts its modes only."""
+    import subprocess
+    import sys
+    code = ("import ctypes, sys; sys.path.insert(0, %r); import paper_2109_14704_amd as H; "
+            "L = H.lib(); print(L.hentt_ntt_fwd(None, None, 1, None), L.hentt_ct_tensor_grouped(None, 1, 0, None))" % ROOT)
+    env = dict(os.environ, HENTT_ROCTX="1")
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.split() == ["-1", "-1"]
+    from paper_2109_14704_amd import autotune
+    os.environ["HENTT_TUNE"] = "bogus"
+    try:
+        with pytest.raises(ValueError):
+            autotune.tune_mode()
+        for m in ("cached", "force", "off"):
+            os.environ["HENTT_TUNE"] = m
+            assert autotune.tune_mode() == m
+    finally:
+        del os.environ["HENTT_TUNE"]
