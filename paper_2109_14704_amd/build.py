@@ -50,28 +50,35 @@ def build(verbose=False, jobs=None):
     mb_tmp = MB_OUT + ".tmp%d" % os.getpid()
     mb_cmd = [_hipcc()] + HIPCC_FLAGS + ["-shared", "-o", mb_tmp, MB_SRC] if os.path.exists(MB_SRC) else None
     jobs = jobs or min(8, os.cpu_count() or 1)
-    with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
-        futs = []
-        for c, s in zip(cmds, srcs):
-            if verbose:
-                print(" ".join(c), flush=True)
-            futs.append(ex.submit(_run, c, os.path.basename(s)))
-        if mb_cmd:
-            if verbose:
-                print(" ".join(mb_cmd), flush=True)
-            futs.append(ex.submit(_run, mb_cmd, "libhentt_mb.so"))
-        for f in futs:
-            f.result()
-    for o in objs:
-        os.replace(o + ".tmp%d" % os.getpid(), o)
     tmp = OUT + ".tmp%d" % os.getpid()
-    link = [_hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
-    if verbose:
-        print(" ".join(link), flush=True)
-    _run(link, "libhentt.so")
-    os.replace(tmp, OUT)
-    if mb_cmd:
-        os.replace(mb_tmp, MB_OUT)
+    temps = [o + ".tmp%d" % os.getpid() for o in objs] + [tmp] + ([mb_tmp] if mb_cmd else [])
+    try:
+        with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
+            futs = []
+            for c, s in zip(cmds, srcs):
+                if verbose:
+                    print(" ".join(c), flush=True)
+                futs.append(ex.submit(_run, c, os.path.basename(s)))
+            if mb_cmd:
+                if verbose:
+                    print(" ".join(mb_cmd), flush=True)
+                futs.append(ex.submit(_run, mb_cmd, "libhentt_mb.so"))
+            for f in futs:
+                f.result()
+        for o in objs:
+            os.replace(o + ".tmp%d" % os.getpid(), o)
+        link = [_hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+        if verbose:
+            print(" ".join(link), flush=True)
+        _run(link, "libhentt.so")
+        os.replace(tmp, OUT)
+        if mb_cmd:
+            os.replace(mb_tmp, MB_OUT)
+    finally:
+        # a failed compile leaves no partial outputs behind
+        for t in temps:
+            if os.path.exists(t):
+                os.remove(t)
     return OUT
 
 
