@@ -34,12 +34,12 @@ enum { BATCH_B = 12, BATCH_E = 4, BATCH_LANES = 256 };
 
 // Forward block pass (stages logn-12 .. logn-1) on the 2^12 words at p.
 __device__ __forceinline__ void batch_fwd_block(uint64_t *p, uint32_t blockStart, uint32_t logn, const Tw *t,
-                                                const ModQ &m, uint64_t *lds, uint32_t tid) {
+                                                const LimbConst &c, uint64_t *lds, uint32_t tid) {
   using F = FwdFirst<BATCH_B, BATCH_E>;
   uint64_t v[1 << BATCH_E];
   load_global<BATCH_B, BATCH_E, F::LO, F::R>(v, p, RoundMap<BATCH_B, BATCH_E, F::LO, F::R>::lane_part(tid));
-  fwd_block_rounds<BATCH_B, BATCH_E, F::LO, F::R>(v, logn, lds, tid, blockStart, t, m);
-  reduce_fwd<BATCH_E>(v, m);
+  fwd_block_rounds<BATCH_B, BATCH_E, F::LO, F::R>(v, logn, lds, tid, blockStart, t, c.m);
+  reduce_fwd<BATCH_E>(v, c.m, c.mu, c.k);
   store_global_m0<BATCH_B, BATCH_E>(v, p, lds, tid);
 }
 
@@ -176,9 +176,9 @@ __global__ __launch_bounds__(BATCH_LANES, 4) void k_batch(const BatchUnit *__res
       }
     }
     if constexpr (!INV) {
-      if (kind == BT_WHOLE) batch_fwd_block(u.data, 0, BATCH_B, u.tw, c.m, lds, tid);
+      if (kind == BT_WHOLE) batch_fwd_block(u.data, 0, BATCH_B, u.tw, c, lds, tid);
       else if (kind == BT_PASS1) batch_cols_any<false>(u.logn, u.data, idx, tid, u.tw, c);
-      else batch_fwd_block(u.data + ((uint64_t)idx << BATCH_B), idx << BATCH_B, u.logn, u.tw, c.m, lds, tid);
+      else batch_fwd_block(u.data + ((uint64_t)idx << BATCH_B), idx << BATCH_B, u.logn, u.tw, c, lds, tid);
     } else {
       if (kind == BT_WHOLE) batch_inv_block(u.data, 0, BATCH_B, u.tw, c, lds, tid);
       else if (kind == BT_PASS1) batch_inv_block(u.data + ((uint64_t)idx << BATCH_B), idx << BATCH_B, u.logn, u.tw, c, lds, tid);

@@ -114,6 +114,30 @@ __device__ __forceinline__ uint64_t reduce_16q(uint64_t x, const ModQ &m) {
   return csubn(csubn(csubn(csubn(x, m.nq4 + m.nq4), m.nq4), m.nq2), m.nq);
 }
 
+// Any x < 2^64 to [0, 2q) by a quotient estimate, for q > 2^33 (bit length
+// k >= 34), with c = floor(2^(k+31) / q) (below 2^32) and sh = k - 33:
+// e = floor(hi32(x) c / 2^(k-1)) never exceeds x / q and falls short of it
+// by less than 2 (the low word of x weighs less than 2^32 / q < 1/2, the
+// truncation of c less than hi32(x) / 2^(k-1) < 1/2, the floor less than 1),
+// so x - e q lies in [0, 2q).  One multiply-high, a shift and the 32 x 64-bit
+// product e q, against a chain of conditional subtractions.
+__device__ __forceinline__ uint64_t reduce_est(uint64_t x, uint64_t nq, uint32_t c, uint32_t sh) {
+  const uint32_t e = __umulhi(hi32(x), c) >> sh;
+  // x - e q (mod 2^64): the low product in the multiply-add's accumulator,
+  // e times the high word of -q added to the high word alone
+  const uint64_t r = mad32(e, lo32(nq), x);
+  uint32_t t = e * hi32(nq);
+#ifndef HENTT_HOST_TEST
+  // kept a plain multiply and add: fused into one more 32x32+64 multiply-add
+  // it costs two register moves
+  asm("" : "+v"(t));
+#endif
+  return ((uint64_t)(hi32(r) + t) << 32) | lo32(r);
+}
+// c of reduce_est from the Barrett constant mu = floor(2^(2k) / q):
+// floor(mu / 2^(k-31)) = floor(2^(k+31) / q).
+__device__ __forceinline__ uint32_t est_c(uint64_t mu, uint32_t k) { return (uint32_t)(mu >> (k - 31)); }
+
 // Barrett reduction of a 128-bit z < 2^(2k+1) modulo q, 2^(k-1) <= q < 2^k
 // (k <= 60), with mu = floor(2^(2k) / q): quotient estimate
 // floor(floor(z / 2^(k-1)) * mu / 2^(k+1)) is short by at most 3.

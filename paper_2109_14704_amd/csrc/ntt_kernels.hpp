@@ -243,10 +243,21 @@ __device__ __forceinline__ void load_global_m0(uint64_t (&x)[1 << E], const uint
 #endif
 }
 
-// Canonical reductions of forward outputs ([0, 16q)) and inverse outputs ([0, 4q)).
-template <int E> __device__ __forceinline__ void reduce_fwd(uint64_t (&x)[1 << E], const ModQ &m) {
+// Canonical reductions of forward outputs ([0, 16q)) and inverse outputs
+// ([0, 4q)).  Forward: moduli above 2^33 (bit length k >= 34; mu is the
+// limb's Barrett constant) take the quotient estimate and one conditional
+// subtraction, smaller ones the chain of four conditional subtractions (k
+// is uniform per workgroup, so the branch is a scalar one).
+template <int E>
+__device__ __forceinline__ void reduce_fwd(uint64_t (&x)[1 << E], const ModQ &m, uint64_t mu, uint32_t k) {
+  if (k >= 34) {
+    const uint32_t c = est_c(mu, k), sh = k - 33;
 #pragma unroll
-  for (int s = 0; s < (1 << E); ++s) x[s] = reduce_16q(x[s], m);
+    for (int s = 0; s < (1 << E); ++s) x[s] = csubn(reduce_est(x[s], m.nq, c, sh), m.nq);
+  } else {
+#pragma unroll
+    for (int s = 0; s < (1 << E); ++s) x[s] = reduce_16q(x[s], m);
+  }
 }
 template <int E> __device__ __forceinline__ void reduce_inv(uint64_t (&x)[1 << E], const ModQ &m) {
 #pragma unroll
@@ -339,7 +350,7 @@ __global__ __launch_bounds__(1 << (LOGN - E)) void k_fwd_whole(uint64_t* __restr
   uint64_t v[1 << E];
   load_global<LOGN, E, F::LO, F::R>(v, p, RoundMap<LOGN, E, F::LO, F::R>::lane_part(tid));
   fwd_block_rounds<LOGN, E, F::LO, F::R>(v, LOGN, lds, tid, 0, t, m);
-  reduce_fwd<E>(v, m);
+  reduce_fwd<E>(v, m, lc[un.limb].mu, lc[un.limb].k);
   store_global_m0<LOGN, E>(v, p, lds, tid);
 }
 
@@ -479,7 +490,7 @@ __global__ __launch_bounds__(1 << (B - E)) void k_fwd_blocks(uint64_t *__restric
   uint64_t v[1 << E];
   load_global<B, E, F::LO, F::R>(v, p, RoundMap<B, E, F::LO, F::R>::lane_part(tid));
   fwd_block_rounds<B, E, F::LO, F::R>(v, LOGN, lds, tid, blockStart, t, m);
-  reduce_fwd<E>(v, m);
+  reduce_fwd<E>(v, m, lc[un.limb].mu, lc[un.limb].k);
   store_global_m0<B, E>(v, p, lds, tid);
 }
 
@@ -591,7 +602,14 @@ __device__ __forceinline__ void products_mont(uint64_t (&X)[ProdShape<MODE>::NIN
 }
 
 // Forward outputs ([0, 16q)) brought to the factor range of products_mont.
-template <int MODE, int E> __device__ __forceinline__ void reduce_for_mont(uint64_t (&x)[1 << E], const ModQ &m) {
+template <int MODE, int E>
+__device__ __forceinline__ void reduce_for_mont(uint64_t (&x)[1 << E], const ModQ &m, uint64_t mu, uint32_t k) {
+  if (k >= 34) {  // quotient estimate: [0, 2q) for either product
+    const uint32_t c = est_c(mu, k), sh = k - 33;
+#pragma unroll
+    for (int s = 0; s < (1 << E); ++s) x[s] = reduce_est(x[s], m.nq, c, sh);
+    return;
+  }
 #pragma unroll
   for (int s = 0; s < (1 << E); ++s) {
     x[s] = csubn(csubn(x[s], m.nq4 + m.nq4), m.nq4);
@@ -647,8 +665,8 @@ __device__ __forceinline__ void prod_block(const ProdArgs &a, const Tw *__restri
       const Tw *tp = opaque(t);
       load_global<B, E, F::LO, F::R, true>(v, pick_ptr(a.in, p) + in_off, RoundMap<B, E, F::LO, F::R>::lane_part(tid));
       fwd_block_rounds<B, E, F::LO, F::R>(v, LOGN, lds, tid, blockStart, tp, c.m);
-      if constexpr (DO_INV) reduce_for_mont<MODE, E>(v, c.m);
-      else reduce_fwd<E>(v, c.m);
+      if constexpr (DO_INV) reduce_for_mont<MODE, E>(v, c.m, c.mu, c.k);
+      else reduce_fwd<E>(v, c.m, c.mu, c.k);
     } else {
       load_global_m0<B, E, true>(v, pick_ptr(a.in, p) + in_off, lds, tid);
     }

@@ -66,7 +66,7 @@ __global__ __launch_bounds__(1 << (LOGN - E)) void k_rs_whole(RsArgs a, const Tw
 #pragma unroll
   for (int s = 0; s < (1 << E); ++s) v[s] = rs_prologue(v[s], a.qL, a.h, r, m.q);
   fwd_block_rounds<LOGN, E, F::LO, F::R>(v, LOGN, lds, tid, 0, t, m);
-  reduce_fwd<E>(v, m);
+  reduce_fwd<E>(v, m, lc[i].mu, lc[i].k);
   uint64_t cv[1 << E];
   load_global_m0<LOGN, E>(cv, a.c + (((uint64_t)b * (a.L + 1) + i) << LOGN), lds, tid);
 #pragma unroll
@@ -115,7 +115,7 @@ __global__ __launch_bounds__(1 << (B - E)) void k_rs_blocks(RsArgs a, const Tw *
   uint64_t v[1 << E];
   load_global<B, E, F::LO, F::R>(v, p, RoundMap<B, E, F::LO, F::R>::lane_part(tid));
   fwd_block_rounds<B, E, F::LO, F::R>(v, LOGN, lds, tid, blockStart, tw + (size_t)i * 2 * (1u << LOGN), m);
-  reduce_fwd<E>(v, m);
+  reduce_fwd<E>(v, m, lc[i].mu, lc[i].k);
   uint64_t cv[1 << E];
   load_global_m0<B, E>(cv, a.c + (((uint64_t)b * (a.L + 1) + i) << LOGN) + blockStart, lds, tid);
 #pragma unroll

@@ -1,7 +1,8 @@
 // CPU property test of the device modular arithmetic (modarith.hpp built for
 // the host).  Checks the forward butterflies' contracts (the classic one in
 // [0, 8q) and the library's alternating one in [0, 16q); X' = X + W Y,
-// Y' = X - W Y mod q), the inverse butterfly's [0, 4q) contract,
+// Y' = X - W Y mod q), the inverse butterfly's [0, 4q) contract, the
+// quotient-estimate reduction of any 64-bit word to [0, 2q),
 // the Barrett/Shoup/mad_mod products and the Montgomery reduction against
 // exact 128-bit arithmetic.
 #include <stdint.h>
@@ -68,6 +69,19 @@ int main(int argc, char **argv) {
     EXPECT(xc % q == (Xc % q + wyw) % q && yc % q == (Xc % q + q - wyw) % q, "ct16 corrected value\n");
     EXPECT(xu % q == (Xu % q + wyw) % q && yu % q == (Xu % q + q - wyw) % q, "ct16 uncorrected value\n");
     EXPECT(reduce_16q(Xc, m) == Xc % q, "reduce_16q\n");
+    // quotient-estimate reduction (q > 2^33): any 64-bit x to [0, 2q), with c
+    // derived from the Barrett constant as the kernels derive it
+    if (k >= 34) {
+      uint64_t mub = (uint64_t)(((u128)1 << (2 * k)) / q);
+      uint32_t c = est_c(mub, (uint32_t)k);
+      EXPECT((u128)c == (((u128)1 << (k + 31)) / q), "est_c q=%llx\n", (unsigned long long)q);
+      const uint64_t xs[6] = {g(), ~0ull, Xc, q16 - 1, (g() % 16) * q, (g() % 16 + 1) * q - 1};
+      for (uint64_t xe : xs) {
+        uint64_t r = reduce_est(xe, m.nq, c, (uint32_t)k - 33);
+        EXPECT(r < 2 * q && r % q == xe % q, "reduce_est q=%llx x=%llx\n", (unsigned long long)q,
+               (unsigned long long)xe);
+      }
+    }
     // inverse butterfly, lazy range [0, 4q)
     uint64_t Xi = (it % 7 == 0) ? 4 * q - 1 : g() % (4 * q), Yi = (it % 6 == 0) ? 4 * q - 1 : g() % (4 * q);
     uint64_t x2 = Xi, y2 = Yi;
