@@ -4,9 +4,11 @@
 //     read-only sweep, 16-byte accesses, grid-stride;
 //   * VALU issue rate of the 32-bit integer multiplies the modular
 //     arithmetic is built from (v_mad_u64_u32, v_mul_hi_u32, v_mul_lo_u32),
-//     of a plain v_add_u32 for comparison, and of the library's own lazy
-//     forward butterfly (multiplies, additions, compares and selects as the
-//     kernels issue them).
+//     of the other instructions its butterflies issue (the 64-bit add
+//     v_lshl_add_u64, the 64-bit compare, the three-input add, register
+//     moves), of a plain v_add_u32 for comparison, and of the library's own
+//     lazy forward butterfly (multiplies, additions, compares and selects as
+//     the kernels issue them).
 // Every issue kernel keeps 8 independent dependency chains per lane and
 // writes every chain's final value, so no operation can be removed or
 // hoisted; the single-instruction kernels spell the instruction in inline
@@ -50,7 +52,8 @@ __global__ __launch_bounds__(256) void mb_read_k(const u64x2 *__restrict__ src, 
   out[(uint64_t)blockIdx.x * 256 + threadIdx.x] = acc;
 }
 
-enum { MB_MAD64 = 0, MB_MULHI = 1, MB_MULLO = 2, MB_ADD = 3, MB_BFLY = 4 };
+enum { MB_MAD64 = 0, MB_MULHI = 1, MB_MULLO = 2, MB_ADD = 3, MB_BFLY = 4, MB_ADD64 = 5, MB_CMP64 = 6, MB_ADD3 = 7,
+       MB_MOV = 8 };
 
 // The butterfly's constants arrive as kernel arguments, as the library's
 // kernels load theirs from memory, so that the compiler cannot specialise
@@ -88,6 +91,29 @@ __global__ __launch_bounds__(256) void mb_issue_k(uint64_t *out, uint32_t iters,
 #pragma unroll
     for (int j = 0; j < 8; ++j) r ^= acc[j];
     out[gid] = r;
+  } else if constexpr (KIND == MB_ADD64 || KIND == MB_CMP64) {
+    uint64_t z[8];
+    const uint64_t a64 = ((uint64_t)a << 32) | (a ^ 0x5555u);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) z[j] = gid * 8 + j;
+    uint32_t hits = 0;
+    for (uint32_t it = 0; it < iters; ++it) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        if constexpr (KIND == MB_ADD64) {
+          asm volatile("v_lshl_add_u64 %0, %0, 0, %1" : "+v"(z[j]) : "v"(a64));
+        } else {
+          // the compare's result lands in VCC and is not read: the chain
+          // is the compare itself, one per element and iteration
+          asm volatile("v_cmp_lt_u64 vcc, %0, %1" ::"v"(z[j]), "v"(a64) : "vcc");
+        }
+      }
+      hits += 1;
+    }
+    uint64_t r = hits;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) r ^= z[j];
+    out[gid] = r;
   } else {
     uint32_t x[8];
 #pragma unroll
@@ -97,6 +123,8 @@ __global__ __launch_bounds__(256) void mb_issue_k(uint64_t *out, uint32_t iters,
       for (int j = 0; j < 8; ++j) {
         if constexpr (KIND == MB_MULHI) asm volatile("v_mul_hi_u32 %0, %0, %1" : "+v"(x[j]) : "v"(a));
         else if constexpr (KIND == MB_MULLO) asm volatile("v_mul_lo_u32 %0, %0, %1" : "+v"(x[j]) : "v"(a));
+        else if constexpr (KIND == MB_ADD3) asm volatile("v_add3_u32 %0, %0, %1, %1" : "+v"(x[j]) : "v"(a));
+        else if constexpr (KIND == MB_MOV) asm volatile("v_mov_b32 %0, %1" : "=v"(x[j]) : "v"(x[(j + 1) & 7]));
         else asm volatile("v_add_u32 %0, %0, %1" : "+v"(x[j]) : "v"(a));
       }
     }
@@ -134,7 +162,8 @@ int mb_read(const void *src, uint64_t bytes, uint64_t *out, uint32_t grid, void 
 }
 
 // Issue-rate kernel `kind` (0 v_mad_u64_u32, 1 v_mul_hi_u32, 2 v_mul_lo_u32,
-// 3 v_add_u32, 4 forward butterfly): grid workgroups of 256 lanes, each lane
+// 3 v_add_u32, 4 forward butterfly, 5 v_lshl_add_u64, 6 v_cmp_lt_u64,
+// 7 v_add3_u32, 8 v_mov_b32): grid workgroups of 256 lanes, each lane
 // running 8 chains of `iters` operations; out receives grid * 256 words.
 // For kind 4, w, ws, q are a twiddle, its Shoup quotient and the modulus.
 int mb_issue(int kind, uint64_t *out, uint32_t iters, uint32_t grid, uint32_t a, uint64_t w, uint64_t ws, uint64_t q,
@@ -148,6 +177,10 @@ int mb_issue(int kind, uint64_t *out, uint32_t iters, uint32_t grid, uint32_t a,
     case MB_MULLO: hipLaunchKernelGGL(mb_issue_k<MB_MULLO>, dim3(grid), dim3(256), 0, st, out, iters, a, w, ws, m); break;
     case MB_ADD: hipLaunchKernelGGL(mb_issue_k<MB_ADD>, dim3(grid), dim3(256), 0, st, out, iters, a, w, ws, m); break;
     case MB_BFLY: hipLaunchKernelGGL(mb_issue_k<MB_BFLY>, dim3(grid), dim3(256), 0, st, out, iters, a, w, ws, m); break;
+    case MB_ADD64: hipLaunchKernelGGL(mb_issue_k<MB_ADD64>, dim3(grid), dim3(256), 0, st, out, iters, a, w, ws, m); break;
+    case MB_CMP64: hipLaunchKernelGGL(mb_issue_k<MB_CMP64>, dim3(grid), dim3(256), 0, st, out, iters, a, w, ws, m); break;
+    case MB_ADD3: hipLaunchKernelGGL(mb_issue_k<MB_ADD3>, dim3(grid), dim3(256), 0, st, out, iters, a, w, ws, m); break;
+    case MB_MOV: hipLaunchKernelGGL(mb_issue_k<MB_MOV>, dim3(grid), dim3(256), 0, st, out, iters, a, w, ws, m); break;
     default: return -1;
   }
   return hipGetLastError() == hipSuccess ? 0 : -4;

@@ -9,6 +9,8 @@ known work:
   * hbm_read: each byte read once;
   * mad64 / mulhi / mullo / add: lane-operations per second of
     v_mad_u64_u32, v_mul_hi_u32, v_mul_lo_u32, v_add_u32;
+  * add64 / cmp64 / add3 / mov: the same for the other instructions the
+    butterflies issue (v_lshl_add_u64, v_cmp_lt_u64, v_add3_u32, v_mov_b32);
   * mul_mix: the rate of the Shoup butterfly's own multiply mix (3
     v_mad_u64_u32, 2 v_mul_hi_u32, 4 v_mul_lo_u32 per butterfly), i.e. nine
     multiplies in the time the three measured rates give them;
@@ -24,7 +26,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhentt_mb.so")
 _lib = None
 
-MB_MAD64, MB_MULHI, MB_MULLO, MB_ADD, MB_BFLY = range(5)
+MB_MAD64, MB_MULHI, MB_MULLO, MB_ADD, MB_BFLY, MB_ADD64, MB_CMP64, MB_ADD3, MB_MOV = range(9)
 
 
 def lib():
@@ -125,6 +127,10 @@ def measure_all(detail=None):
         "mulhi_tops": issue_rate(MB_MULHI) / 1e12,
         "mullo_tops": issue_rate(MB_MULLO) / 1e12,
         "add_tops": issue_rate(MB_ADD) / 1e12,
+        "add64_tops": issue_rate(MB_ADD64) / 1e12,
+        "cmp64_tops": issue_rate(MB_CMP64) / 1e12,
+        "add3_tops": issue_rate(MB_ADD3) / 1e12,
+        "mov_tops": issue_rate(MB_MOV) / 1e12,
         "bfly_gbfly_s": issue_rate(MB_BFLY) / 1e9,
     }
     # the butterfly's nine multiplies at the measured rates of their kinds
