@@ -153,10 +153,13 @@ def setup(name, torch, H, grid_arg=0):
         xs = [to_dev(workloads.uneven_operand(j, ln, L, mods), torch) for j, (ln, L) in enumerate(jobs)]
         spec = [(x, tables[ln], L) for x, (ln, L) in zip(xs, jobs)]
         plan_f, plan_i = H.BatchPlan(spec, +1), H.BatchPlan(spec, -1)
-        grid, look, group = _tuned_grid(plan_f, grid_arg, xs)
-        for p in (plan_f, plan_i):
+        # each direction at its own tuned schedule (any canonical words are valid inverse inputs)
+        sched = {}
+        for nm, p in (("fwd", plan_f), ("inv", plan_i)):
+            grid, look, group = _tuned_grid(p, grid_arg, xs)
             p.set_grid(grid)
             p.set_schedule(look, group)
+            sched[nm] = {"persistent_grid": grid, "pass2_lookahead_pct": look, "group_units": group}
         plan_f.capture()
         plan_i.capture()
         coeffs = sum(L << ln for ln, L in jobs)
@@ -190,7 +193,7 @@ def setup(name, torch, H, grid_arg=0):
 
         info = {"workload": "uneven", "jobs": len(jobs), "N_range": [1 << 12, 1 << 17], "limbs_range": [1, 32],
                 "coefficients": coeffs, "ops": "fwd then inv, each one persistent launch, hipGraph replay",
-                "persistent_grid": grid, "pass2_lookahead_pct": look, "group_units": group}
+                "schedule": sched}
         return dict(step=step, per_poly=per_poly_step, coeffs=2 * coeffs, info=info, kernel_work=kw,
                     step_work=direction + direction, cpu=lambda k: cpu_uneven(jobs, mods, k),
                     cpu1=lambda k: cpu_uneven(jobs, mods, k, threads=1), sample_limit=len(jobs), check=check,

@@ -446,6 +446,7 @@ class BatchPlan:
         h = _VP()
         _check(lib().hentt_batch_plan_create(arr, len(jobs), int(direction), ctypes.byref(h)), "plan_create")
         self._h = h
+        self.direction = +1 if int(direction) > 0 else -1
         self._graph = None
 
     def info(self):

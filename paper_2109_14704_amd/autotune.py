@@ -83,21 +83,39 @@ def _time(fn, reps=10, warm=10):
     return a.elapsed_time(b) / reps
 
 
-def _gated_choice(candidates, apply, run, data, check, restore_every_run):
+def _gated_choice(candidates, apply, run, data, check, restore_every_run, finish=None, retime=3):
     """Shared candidate loop.  apply(c) selects candidate c; run() computes the
-    outputs in `data` (in place) from the snapshot; returns (best, table)."""
+    outputs in `data` (in place) from the snapshot; finish() (optional) raises
+    if the runs since the last call went wrong (called after the parity run
+    and after each timing, not inside the timed loop).  The `retime` fastest
+    candidates are timed once more, each keeping its better time, so that one
+    noisy measurement does not decide.  Returns (best, table)."""
     snapshot = [d.clone() for d in data]
 
     def restore():
         for d, s in zip(data, snapshot):
             d.copy_(s)
 
-    best, best_ms, ref, table = None, None, None, {}
+    def timing():
+        if restore_every_run:
+            def timed():
+                restore()
+                run()
+            ms = _time(timed)
+        else:
+            ms = _time(run)
+        if finish is not None:
+            finish()
+        return ms
+
+    ref, table, ms_of = None, {}, {}
     for i, c in enumerate(candidates):
         apply(c)
         restore()
         run()
         torch.cuda.synchronize()
+        if finish is not None:
+            finish()
         out = [d.clone() for d in data]
         if i == 0:
             if check is not None and not check(out):
@@ -107,16 +125,14 @@ def _gated_choice(candidates, apply, run, data, check, restore_every_run):
         elif not all(torch.equal(x, y) for x, y in zip(out, ref)):
             table[str(c)] = "differs"
             continue                       # parity gate: a candidate that disagrees is never chosen
-        if restore_every_run:
-            def timed():
-                restore()
-                run()
-            ms = _time(timed)
-        else:
-            ms = _time(run)
+        ms_of[c] = timing()
+    for c in sorted(ms_of, key=ms_of.get)[:retime]:
+        apply(c)
+        restore()
+        ms_of[c] = min(ms_of[c], timing())
+    for c, ms in ms_of.items():
         table[str(c)] = round(ms, 4)
-        if best_ms is None or ms < best_ms:
-            best, best_ms = c, ms
+    best = min(ms_of, key=ms_of.get)
     restore()
     return best, table
 
@@ -134,7 +150,10 @@ def persistent_grid(plan, data, candidates=None, check=None, force=False):
         return plan.info()["grid"], 200, 8
     force = force or mode == "force"
     info = plan.info()
-    key = "grid/%s/%s/units%d/tiles%d" % (_arch(), source_digest(), info["units"], info["tiles"])
+    # the two directions tune apart: their pass-2 tiles wait on different
+    # pass-1 work (column tiles forward, 2^12 blocks inverse)
+    key = "grid/%s/%s/%s/units%d/tiles%d" % (_arch(), source_digest(), "fwd" if plan.direction > 0 else "inv",
+                                            info["units"], info["tiles"])
     cache = _load()
     if key in cache and not force:
         grid, look, group = cache[key]["choice"]
@@ -144,7 +163,8 @@ def persistent_grid(plan, data, candidates=None, check=None, force=False):
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     candidates = candidates or [(2 * cus, 200, 8), (4 * cus, 200, 8), (3 * cus, 200, 8), (4 * cus, 100, 8),
                                 (4 * cus, 50, 8), (4 * cus, 200, 1), (4 * cus, 200, 4), (4 * cus, 200, 16),
-                                (4 * cus, 200, 64), (4 * cus, 400, 8)]
+                                (4 * cus, 200, 64), (4 * cus, 400, 8), (4 * cus, 300, 1), (4 * cus, 400, 1),
+                                (4 * cus, 600, 1)]
 
     def apply(c):
         plan.set_grid(c[0])
@@ -152,9 +172,11 @@ def persistent_grid(plan, data, candidates=None, check=None, force=False):
 
     def run():
         plan.run()
-        plan.status()                      # a tile that gave up waiting fails the candidate loudly
 
-    best, table = _gated_choice(candidates, apply, run, data, check, restore_every_run=False)
+    # a tile that gave up waiting fails the candidate loudly (the error flag
+    # is sticky until the next run resets it, so the last run is checked)
+    best, table = _gated_choice(candidates, apply, run, data, check, restore_every_run=False,
+                                finish=plan.status)
     apply(best)
     cache = _load()
     cache[key] = {"choice": list(best), "ms": table}

@@ -84,14 +84,21 @@ def test_uneven_512_jobs_tuned_graph_replay(gpu, full_uneven, tmp_path, monkeypa
     print("case uneven 512 jobs: autotuning the persistent grid", flush=True)
     grid, look, group = autotune.persistent_grid(plan_f, devs, check=lambda outs: _equal_all(outs, fw) is None)
     assert grid > 0 and plan_f.info()["grid"] == grid
-    plan_i.set_grid(grid)
-    plan_i.set_schedule(look, group)
     assert _equal_all(devs, xs) is None          # the tuner restored the inputs
+    # the inverse tunes on its own (its own cache entry), gated by the round trip
+    print("case uneven 512 jobs: autotuning the inverse plan", flush=True)
+    for d_, w in zip(devs, fw):
+        d_.copy_(dev(w, d_.device))
+    grid_i, look_i, group_i = autotune.persistent_grid(plan_i, devs, check=lambda outs: _equal_all(outs, xs) is None)
+    assert grid_i > 0 and plan_i.info()["grid"] == grid_i
+    assert _equal_all(devs, fw) is None
+    for d_, w in zip(devs, xs):
+        d_.copy_(dev(w, d_.device))
     plan_f.capture()
     plan_i.capture()
     for rep in range(2):
-        print("case uneven 512 jobs: graph replay %d at grid %d, lookahead %d%%, groups of %d" % (rep, grid, look, group),
-              flush=True)
+        print("case uneven 512 jobs: graph replay %d at (%d, %d%%, %d) forward, (%d, %d%%, %d) inverse"
+              % (rep, grid, look, group, grid_i, look_i, group_i), flush=True)
         plan_f.replay()
         plan_f.status()
         assert _equal_all(devs, fw) is None, rep
