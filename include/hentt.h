@@ -296,7 +296,9 @@ int hentt_ntt_batch_status(const hentt_job *jobs, uint32_t njobs, int dir);
 
 /* Explicit plans for the same persistent launch (for autotuning and graphs).
  * create: validates the jobs and uploads the tile list (synchronous).
- * set_grid: number of persistent workgroups (0 = 2 per compute unit);
+ * set_grid: number of persistent workgroups (0 = as many as the device
+ *   holds at once: the kernel's occupancy per compute unit, 4 on gfx950,
+ *   times the compute units);
  *   HENTT_EBUSY while graphs captured from the plan exist (they hold the
  *   old launch shape).
  * run: enqueues a counter reset kernel and the persistent kernel on stream.

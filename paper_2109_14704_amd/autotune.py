@@ -161,7 +161,7 @@ def persistent_grid(plan, data, candidates=None, check=None, force=False):
         plan.set_schedule(int(look), int(group))
         return int(grid), int(look), int(group)
     cus = torch.cuda.get_device_properties(0).multi_processor_count
-    candidates = candidates or [(2 * cus, 200, 8), (4 * cus, 200, 8), (3 * cus, 200, 8), (4 * cus, 100, 8),
+    candidates = candidates or [(4 * cus, 200, 8), (2 * cus, 200, 8), (3 * cus, 200, 8), (4 * cus, 100, 8),
                                 (4 * cus, 50, 8), (4 * cus, 200, 1), (4 * cus, 200, 4), (4 * cus, 200, 16),
                                 (4 * cus, 200, 64), (4 * cus, 400, 8), (4 * cus, 300, 1), (4 * cus, 400, 1),
                                 (4 * cus, 600, 1)]

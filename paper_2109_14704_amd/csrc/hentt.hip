@@ -250,10 +250,17 @@ namespace {
 
 const uint32_t kSpinLimit = 1u << 22;   // bounded wait of a pass-2 tile (s_sleep 2 per try)
 
+// Every workgroup of the persistent kernel resident at once: the kernel's
+// occupancy per compute unit (LDS and VGPRs allow four 256-lane workgroups on
+// gfx950) times the compute units.
 int default_grid() {
-  int dev = 0, cus = 256;
+  int dev = 0, cus = 256, per_f = 0, per_i = 0;
   if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  return cus * 2;  // the persistent kernel holds many VGPRs: 2 workgroups of 256 lanes per CU
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_f, k_batch<false>, BATCH_LANES, 0) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_i, k_batch<true>, BATCH_LANES, 0) != hipSuccess)
+    per_f = per_i = 2;
+  const int per = per_f < per_i ? per_f : per_i;
+  return cus * (per < 1 ? 1 : per);
 }
 
 void plan_free(hentt_batch_plan *p) {

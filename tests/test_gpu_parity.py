@@ -492,6 +492,8 @@ def test_batch_plan_all_sizes(gpu):
     for direction in (+1, -1):
         devs = [dev(x, gpu) for x in xs]
         plan = H.BatchPlan([(d_, tables[ln], L) for d_, (ln, L) in zip(devs, jobs)], direction)
+        # the default grid: every workgroup resident at once (four 256-lane workgroups per CU on gfx950)
+        assert plan.info()["grid"] == 4 * torch.cuda.get_device_properties(0).multi_processor_count
         plan.run()
         plan.status()
         _check_uneven(xs, devs, jobs, mods, direction)
