@@ -48,7 +48,7 @@ __device__ __forceinline__ void batch_inv_block(uint64_t *p, uint32_t blockStart
                                                 const LimbConst &c, uint64_t *lds, uint32_t tid) {
   using L = InvLast<BATCH_B, BATCH_E>;
   uint64_t v[1 << BATCH_E];
-  load_global_m0<BATCH_B, BATCH_E>(v, p, lds, tid);
+  load_global_m0_fresh<BATCH_B, BATCH_E>(v, p, lds, tid);  // the previous tile ended with a barrier
   inv_block_rounds<BATCH_B, BATCH_E, 0, BATCH_E>(v, logn, lds, tid, blockStart, it, c);
   if (logn == BATCH_B) reduce_inv<BATCH_E>(v, c.m);
   store_global<BATCH_B, BATCH_E, L::LO, L::R>(v, p, RoundMap<BATCH_B, BATCH_E, L::LO, L::R>::lane_part(tid));
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(BATCH_LANES, 4) void k_batch(const BatchUnit *__res
                                                        const uint32_t *__restrict__ qoff,
                                                        const uint32_t *__restrict__ qmap, uint32_t *ctl,
                                                        uint32_t spin_limit) {
-  __shared__ uint64_t lds[LdsSize<BATCH_B>::value];
+  __shared__ __attribute__((aligned(16))) uint64_t lds[LdsSize<BATCH_B>::value];
   __shared__ uint32_t s_tile, s_ok;
   const uint32_t q = qmap[xcc_id()];
   if (q >= BATCH_NQ) return;  // an XCD the plan did not see: its queue is served elsewhere

@@ -165,6 +165,7 @@ __device__ __forceinline__ void inv_round(uint64_t (&x)[1 << E], uint32_t logn, 
 // streaming accesses (the forward block pass at N = 2^15 took twice as long)
 // and use ordinary ones.
 #define HENTT_GLOBAL __attribute__((address_space(1)))
+typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
 template <bool NT> __device__ __forceinline__ uint64_t gload(const uint64_t* base, uint32_t i) {
   const HENTT_GLOBAL uint64_t* p = (const HENTT_GLOBAL uint64_t*)((const HENTT_GLOBAL char*)base + (i << 3));
   if constexpr (NT) return __builtin_nontemporal_load(p);
@@ -241,6 +242,47 @@ __device__ __forceinline__ void load_global_m0(uint64_t (&x)[1 << E], const uint
 #else
   load_global<B, E, 0, E, NT>(x, src, RoundMap<B, E, 0, E>::lane_part(tid));
 #endif
+}
+
+// The same load for a workgroup whose LDS holds nothing yet (the first
+// access of a kernel or of a persistent tile): direct global-to-LDS loads
+// (global_load_lds_dwordx4), which move each lane's 16 bytes into the wave's
+// 1 KB LDS window without passing through registers, then one 16-byte LDS
+// read per word pair.  One instruction fills a contiguous window, so the LDS
+// layout is set by which global pair each lane fetches: pair P = 8t + k of
+// the block sits at LDS pair 8t + (k ^ (t mod 8)) (the map is its own
+// inverse), which puts the eight pairs one 8-lane group reads in eight
+// different 16-byte bank groups.  Ends with a barrier, like load_global_m0.
+#ifndef HENTT_DMA_LOAD
+#define HENTT_DMA_LOAD 1
+#endif
+__device__ __forceinline__ uint32_t dma_swz(uint32_t pair) { return pair ^ ((pair >> 3) & 7u); }
+template <int B, int E>
+__device__ __forceinline__ void load_global_m0_fresh(uint64_t (&x)[1 << E], const uint64_t* __restrict__ src,
+                                                     uint64_t* lds, uint32_t tid) {
+  constexpr uint32_t LANES = 1u << (B - E);
+  if constexpr (HENTT_DMA_LOAD && LANES % 64 == 0 && E >= 1) {
+    constexpr uint32_t WAVE_WORDS = 64u << E;   // the words one wave moves
+    const uint32_t wave = tid >> 6, lane = tid & 63;
+    typedef __attribute__((address_space(3))) void lds_void;
+#pragma unroll
+    for (uint32_t i = 0; i < WAVE_WORDS / 128; ++i) {
+      const uint32_t win = wave * WAVE_WORDS + 128 * i;   // first word of this instruction's window
+      const uint32_t pair = win / 2 + lane;                  // LDS pair this lane fills
+      __builtin_amdgcn_global_load_lds(src + 2 * dma_swz(pair), (lds_void*)(lds + win), 16, 0, 0);
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+#pragma unroll
+    for (uint32_t j = 0; j < (1u << (E - 1)); ++j) {
+      const u64x2 w = *(const u64x2*)(lds + 2 * dma_swz((tid << (E - 1)) + j));
+      x[2 * j] = w.x;
+      x[2 * j + 1] = w.y;
+    }
+    __syncthreads();
+  } else {
+    load_global_m0<B, E>(x, src, lds, tid);
+  }
 }
 
 // Canonical reductions of forward outputs ([0, 16q)) and inverse outputs
@@ -340,7 +382,7 @@ template <int LOGN, int E>
 __global__ __launch_bounds__(1 << (LOGN - E)) void k_fwd_whole(uint64_t* __restrict__ x, const Tw* __restrict__ tw,
                                                                 const LimbConst* __restrict__ lc, uint32_t batch,
                                                                 uint32_t limbs) {
-  __shared__ uint64_t lds[LdsSize<LOGN>::value];
+  __shared__ __attribute__((aligned(16))) uint64_t lds[LdsSize<LOGN>::value];
   const Unit un = unit_of(blockIdx.x, 1, batch, limbs);
   const ModQ m = lc[un.limb].m;
   const Tw* t = tw + (size_t)un.limb * 2 * (1u << LOGN);
@@ -358,7 +400,7 @@ template <int LOGN, int E>
 __global__ __launch_bounds__(1 << (LOGN - E)) void k_inv_whole(uint64_t* __restrict__ x, const Tw* __restrict__ tw,
                                                                 const LimbConst* __restrict__ lc, uint32_t batch,
                                                                 uint32_t limbs) {
-  __shared__ uint64_t lds[LdsSize<LOGN>::value];
+  __shared__ __attribute__((aligned(16))) uint64_t lds[LdsSize<LOGN>::value];
   const Unit un = unit_of(blockIdx.x, 1, batch, limbs);
   const LimbConst c = lc[un.limb];
   const Tw* it = tw + ((size_t)un.limb * 2 + 1) * (1u << LOGN);
@@ -366,7 +408,7 @@ __global__ __launch_bounds__(1 << (LOGN - E)) void k_inv_whole(uint64_t* __restr
   const uint32_t tid = threadIdx.x;
   using L = InvLast<LOGN, E>;
   uint64_t v[1 << E];
-  load_global_m0<LOGN, E>(v, p, lds, tid);
+  load_global_m0_fresh<LOGN, E>(v, p, lds, tid);
   inv_block_rounds<LOGN, E, 0, (LOGN < E ? LOGN : E)>(v, LOGN, lds, tid, 0, it, c);
   reduce_inv<E>(v, c.m);
   store_global<LOGN, E, L::LO, L::R>(v, p, RoundMap<LOGN, E, L::LO, L::R>::lane_part(tid));
@@ -406,7 +448,6 @@ __device__ __forceinline__ void col_pass(const uint64_t *src, uint64_t *dst, uin
 // more than the wider accesses gain (measured: column passes of 2^17
 // transforms 12% faster, of the 2^15 and 2^16 products 6-10% slower).
 template <int E> struct ColCpl { static constexpr int value = E <= 4 ? 2 : 1; };
-typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
 // Two neighbouring columns per lane: 16-byte accesses.
 template <int LOGN, int E, bool INV>
 __device__ __forceinline__ void col_pass2(const uint64_t *src, uint64_t *dst, uint32_t col, const Tw *t,
@@ -478,7 +519,7 @@ template <int LOGN, int B, int E>
 __global__ __launch_bounds__(1 << (B - E)) void k_fwd_blocks(uint64_t *__restrict__ x, const Tw *__restrict__ tw,
                                                               const LimbConst *__restrict__ lc, uint32_t batch,
                                                               uint32_t limbs) {
-  __shared__ uint64_t lds[LdsSize<B>::value];
+  __shared__ __attribute__((aligned(16))) uint64_t lds[LdsSize<B>::value];
   constexpr uint32_t tiles = 1u << (LOGN - B);
   const Unit un = unit_of(blockIdx.x, tiles, batch, limbs);
   const ModQ m = lc[un.limb].m;
@@ -499,7 +540,7 @@ template <int LOGN, int B, int E>
 __global__ __launch_bounds__(1 << (B - E)) void k_inv_blocks(uint64_t *__restrict__ x, const Tw *__restrict__ tw,
                                                               const LimbConst *__restrict__ lc, uint32_t batch,
                                                               uint32_t limbs) {
-  __shared__ uint64_t lds[LdsSize<B>::value];
+  __shared__ __attribute__((aligned(16))) uint64_t lds[LdsSize<B>::value];
   constexpr uint32_t tiles = 1u << (LOGN - B);
   const Unit un = unit_of(blockIdx.x, tiles, batch, limbs);
   const LimbConst c = lc[un.limb];
@@ -509,7 +550,7 @@ __global__ __launch_bounds__(1 << (B - E)) void k_inv_blocks(uint64_t *__restric
   const uint32_t tid = threadIdx.x;
   using L = InvLast<B, E>;
   uint64_t v[1 << E];
-  load_global_m0<B, E>(v, p, lds, tid);
+  load_global_m0_fresh<B, E>(v, p, lds, tid);
   inv_block_rounds<B, E, 0, E>(v, LOGN, lds, tid, blockStart, it, c);
   store_global<B, E, L::LO, L::R>(v, p, RoundMap<B, E, L::LO, L::R>::lane_part(tid));
 }
@@ -636,7 +677,7 @@ __device__ __forceinline__ void prod_block(const ProdArgs &a, const Tw *__restri
                                            const LimbConst *__restrict__ lc, const MontLimb *__restrict__ mont,
                                            uint32_t batch, uint32_t limbs, uint32_t blk) {
   constexpr int NIN = ProdShape<MODE>::NIN, NOUT = ProdShape<MODE>::NOUT;
-  __shared__ uint64_t lds[(DO_FWD || DO_INV) ? LdsSize<B>::value : 2];
+  __shared__ __attribute__((aligned(16))) uint64_t lds[(DO_FWD || DO_INV) ? LdsSize<B>::value : 2];
   constexpr uint32_t tiles = 1u << (LOGN - B);
   const uint32_t tile = blk % tiles;
   const uint32_t r = blk / tiles;
