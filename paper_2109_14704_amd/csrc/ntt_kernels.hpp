@@ -643,8 +643,13 @@ __device__ __forceinline__ void products_mont(uint64_t (&X)[ProdShape<MODE>::NIN
 }
 
 // Forward outputs ([0, 16q)) brought to the factor range of products_mont.
+// Factors below 16q already keep a product below q R for q < 2^56
+// (256 q^2 < q 2^64), and the tensor's sum of two products for q < 2^55:
+// such limbs skip the reduction (k, the bit length, is uniform per
+// workgroup, so the test is a scalar branch).
 template <int MODE, int E>
 __device__ __forceinline__ void reduce_for_mont(uint64_t (&x)[1 << E], const ModQ &m, uint64_t mu, uint32_t k) {
+  if (k <= (MODE == PROD_TENSOR ? 55u : 56u)) return;
   if (k >= 34) {  // quotient estimate: [0, 2q) for either product
     const uint32_t c = est_c(mu, k), sh = k - 33;
 #pragma unroll

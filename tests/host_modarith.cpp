@@ -117,6 +117,22 @@ int main(int argc, char **argv) {
     uint64_t a16 = (it % 13 == 1) ? q16 - 1 : g() % q16, kq = (it % 14 == 1) ? q - 1 : g() % q;
     uint64_t x7 = mont_mul(a16, kq, q, qinv);
     EXPECT(x7 < 2 * q && (((u128)x7 << 64) % q) == ((u128)a16 * kq) % q, "mont_mul 16q x q\n");
+    // the fused products' factors straight from a forward pass (below 16q,
+    // no reduction) where the bounds allow it: one product for q < 2^56, the
+    // tensor's sum of two for q < 2^55
+    if (k <= 56) {
+      uint64_t f1 = (it % 15 == 0) ? q16 - 1 : g() % q16, f2 = (it % 16 == 0) ? q16 - 1 : g() % q16;
+      uint64_t x8 = mont_mul(f1, f2, q, qinv);
+      EXPECT(x8 < 2 * q && (((u128)x8 << 64) % q) == ((u128)f1 * f2) % q, "mont_mul 16q x 16q q=%llx\n",
+             (unsigned long long)q);
+    }
+    if (k <= 55) {
+      uint64_t f1 = (it % 15 == 1) ? q16 - 1 : g() % q16, f2 = (it % 16 == 1) ? q16 - 1 : g() % q16;
+      uint64_t f3 = (it % 17 == 1) ? q16 - 1 : g() % q16, f4 = (it % 18 == 1) ? q16 - 1 : g() % q16;
+      uint64_t x9 = mont_mad(f1, f2, f3, f4, q, qinv);
+      u128 T9 = (u128)f1 * f2 + (u128)f3 * f4;
+      EXPECT(x9 < 2 * q && (((u128)x9 << 64) % q) == T9 % q, "mont_mad 16q q=%llx\n", (unsigned long long)q);
+    }
     // the reduction itself at the edge T = q R - 1 and at T = 0
     uint64_t x5 = redc(q - 1, ~0ull, q, qinv), x6 = redc(0, 0, q, qinv);
     EXPECT(x5 < 2 * q && (((u128)x5 << 64) % q) == ((((u128)(q - 1)) << 64) | ~0ull) % q && x6 == 0, "redc edges\n");

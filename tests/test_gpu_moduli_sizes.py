@@ -2,7 +2,9 @@
 outputs (and the reduction ahead of the Montgomery products) takes a quotient
 estimate for moduli above 2^33 and a chain of conditional subtractions below;
 this chain holds NTT primes of 20 to 60 bits, both bit lengths at the switch
-(33 and 34) included, so every kernel family that reduces forward outputs --
+(33 and 34) included, and 55 and 56 bits, the largest sizes at which the fused
+products skip that reduction (the tensor up to 55, the polymul up to 56 bits),
+so every kernel family that reduces forward outputs --
 the two-pass and whole-block transforms, the persistent batch, the fused
 products, rescale -- is compared with the oracle on both sides of it, with
 operands at q - 1 as well as uniform ones."""
@@ -11,7 +13,7 @@ import pytest
 
 import oracle
 
-BITS = [20, 30, 33, 34, 35, 45, 55, 60]
+BITS = [20, 30, 33, 34, 35, 45, 55, 56, 60]
 
 
 def _chain():
