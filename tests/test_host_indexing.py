@@ -4,7 +4,9 @@ stage of the design ladder and its separate reduction launch): the index
 computation of every lane of every workgroup of their launch grids, restated
 here in numpy, stays inside the data, twiddle and constant arrays, and every
 (polynomial, coefficient pair) is visited exactly once per stage.  Shapes:
-the GPU tests' and the ladder benchmark's [1024][8][2^15]."""
+the GPU tests' and the ladder benchmark's [1024][8][2^15].  Also the map of
+the direct-to-LDS first load of inverse blocks (which global pair each lane
+fetches, where each lane reads its words back)."""
 import numpy as np
 import pytest
 
@@ -63,3 +65,38 @@ def test_reduce_launch_lanes_in_bounds(batch, limbs, logn):
     valid = gid < np.uint64(words)
     limb = (gid[valid] >> np.uint64(logn)) % np.uint64(limbs)
     assert int(limb.max()) < limbs and int(gid[valid].max()) == words - 1
+
+
+def dma_swz(pair):
+    """The pair permutation of the direct-to-LDS load (an XOR within groups of eight pairs)."""
+    return pair ^ ((pair >> 3) & 7)
+
+
+@pytest.mark.parametrize("b,e", [(10, 4), (10, 3), (11, 4), (12, 4), (12, 3), (13, 4), (14, 4)])
+def test_direct_lds_load_map(b, e):
+    """The first load of an inverse block (load_global_m0_fresh): restated over
+    every lane of a workgroup of 2^(b-e) lanes.  Every direct-to-LDS
+    instruction fills its wave's 1 KB window with 64 pairs fetched from the
+    block (all in bounds, each LDS pair written once); each lane then reads
+    back exactly its 2^e consecutive words; and the eight pairs an 8-lane
+    group reads at one step lie in eight different 16-byte bank groups."""
+    lanes = 1 << (b - e)
+    assert lanes % 64 == 0
+    wave_words = 64 << e
+    lds_src = np.full(1 << (b - 1), -1, dtype=np.int64)      # global pair held by each LDS pair
+    for wave in range(lanes // 64):
+        for i in range(wave_words // 128):
+            win = wave * wave_words + 128 * i
+            pair = win // 2 + np.arange(64)
+            src = dma_swz(pair)
+            assert src.min() >= 0 and src.max() < (1 << (b - 1))
+            assert (lds_src[pair] == -1).all()                     # each LDS pair written once
+            lds_src[pair] = src
+    assert (lds_src >= 0).all() and len(np.unique(lds_src)) == lds_src.size
+    tid = np.arange(lanes)
+    for j in range(1 << (e - 1)):
+        want = (tid << (e - 1)) + j                                # the lane's j-th pair of consecutive words
+        slot = dma_swz(want)
+        assert (lds_src[slot] == want).all()
+        for g in range(0, lanes, 8):                               # one 8-lane group per 128-byte LDS access
+            assert len(set((slot[g:g + 8] % 8).tolist())) == 8
