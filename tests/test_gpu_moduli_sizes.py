@@ -7,7 +7,8 @@ products skip that reduction (the tensor up to 55, the polymul up to 56 bits),
 so every kernel family that reduces forward outputs --
 the two-pass and whole-block transforms, the persistent batch, the fused
 products, rescale -- is compared with the oracle on both sides of it, with
-operands at q - 1 as well as uniform ones."""
+operands at q - 1 as well as uniform ones (and the grouped tensor, whose jobs
+take different paths within one launch)."""
 import numpy as np
 import pytest
 
@@ -116,3 +117,27 @@ def test_rescale_all_sizes_of_q(gpu, log_n):
     assert np.array_equal(host(H.rescale(t, dev(x, gpu))), oracle.batch_rescale(x, MODS))
     X = oracle.batch_ntt(x, MODS, +1)
     assert np.array_equal(host(H.rescale(t, dev(X, gpu), ntt=True)), oracle.batch_rescale_ntt(X, MODS))
+
+
+@pytest.mark.gpu
+def test_grouped_tensor_all_sizes_of_q(gpu):
+    """The grouped tensor with jobs whose limbs take different reduction paths
+    in one launch (levels 2..9 of the chain at three ring dimensions)."""
+    import torch
+    import paper_2109_14704_amd as H
+    print("case moduli sizes grouped tensor", flush=True)
+    rng = np.random.default_rng(7400)
+    tabs = {ln: H.Tables(ln, MODS) for ln in (13, 14, 15)}
+    spec = [(13, 9), (14, 3), (15, 6), (14, 9), (13, 2), (15, 9)]
+    args, want = [], []
+    for ln, lvl in spec:
+        mods = MODS[:lvl]
+        c = operands(rng, (1, 2, lvl, 1 << ln), mods)
+        d = operands(rng, (1, 2, lvl, 1 << ln), mods)
+        out = torch.full((1, 3, lvl, 1 << ln), -1, dtype=torch.int64, device=gpu)
+        args.append((tabs[ln].view(lvl), dev(c, gpu), dev(d, gpu), out))
+        want.append(oracle.batch_ct_tensor_coeff(c, d, mods))
+    H.ct_tensor_grouped(args)
+    torch.cuda.synchronize()
+    for (ln, lvl), (_, _, _, out), w in zip(spec, args, want):
+        assert np.array_equal(host(out), w), (ln, lvl)
